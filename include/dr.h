@@ -1,0 +1,300 @@
+/*
+ * dr.h — C ABI of the MI355X (gfx950) segmented-range library: for_each,
+ * transform_reduce and inclusive_scan over a distributed range stored as a
+ * table of segments in HBM, through a lazily composed zip/transform view.
+ *
+ * The model (Brock et al., "Distributed Ranges: A Model for Distributed
+ * Data Structures, Algorithms, and Views"):
+ *  - A distributed range is a range whose segments, concatenated in order,
+ *    form the logical range; segments may differ in size (section 3,
+ *    "Distributed Range"). On one GPU the segments are that GPU's share of
+ *    the range, each a contiguous block of HBM (section 3, "Additional
+ *    Concepts": contiguous remote ranges). Here that is the segment table.
+ *  - Views are lazy: zip pairs the elements of aligned ranges, transform
+ *    applies an element-wise function (section 4.4 "Transform", "Zip";
+ *    Algorithm 1 builds a dot product as zip | transform(l*r) | reduce).
+ *    Here that is the view descriptor, evaluated in registers inside the one
+ *    kernel that runs the algorithm (no intermediate array).
+ *  - The algorithms are for_each, reduce and inclusive_scan over the
+ *    segments (section 4.3; Algorithms 3 and 4). Here each is a single
+ *    launch over all segments; the scan's cross-segment offsets travel
+ *    through a decoupled look-back carry chain inside that launch instead of
+ *    the paper's second pass.
+ *
+ * Conventions shared by every entry point:
+ *  - Ownership: the caller owns every buffer (inputs, outputs, the device
+ *    segment table, the workspace, results). The library never allocates
+ *    or frees memory and keeps no state between calls outside the
+ *    caller's workspace.
+ *  - Asynchrony: each call only enqueues work on `stream` (NULL = the
+ *    default stream) and returns; results are valid once the stream's work
+ *    completes. No call synchronises the host except dr_device_status, so
+ *    the calls can be captured into a hipGraph.
+ *  - Errors: arguments are checked on the host before anything is enqueued;
+ *    a failed check returns a negative dr_status and enqueues nothing.
+ *    dr_last_error() gives a readable reason (thread-local). Faults that
+ *    only the device can see (a malformed device table, a look-back that
+ *    never completes, a stale plan) set a flag in the workspace that
+ *    dr_device_status reads; the kernels then skip the work instead of
+ *    touching memory out of range.
+ *  - Workspace: a caller-owned device buffer of dr_workspace_bytes bytes,
+ *    zero-filled once (dr_workspace_init) before its first use. The kernels
+ *    leave it ready for the next call, also under hipGraph replay. Two calls
+ *    that overlap in time must not share a workspace.
+ *  - Alignment: vector loads need no particular alignment from the caller;
+ *    segments whose pointers are misaligned relative to each other fall
+ *    back to element-wise access for that segment.
+ */
+#ifndef DR_H
+#define DR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DR_ABI_VERSION 1
+
+/* Maximum zip arity and number of output streams per segment. */
+#define DR_MAX_ARITY 4
+#define DR_MAX_OUTPUTS 2
+
+/* Tables with more rows than this need a plan (dr_plan) in the workspace;
+ * smaller tables are planned inside every launch. */
+#define DR_SMALL_TABLE 64
+
+typedef enum dr_status {
+    DR_OK = 0,
+    DR_ERR_INVALID_ARG = -1,   /* a malformed argument (see dr_last_error) */
+    DR_ERR_UNSUPPORTED = -2,   /* a dtype/op/out-dtype combination not built */
+    DR_ERR_WORKSPACE = -3,     /* workspace missing, too small or misaligned */
+    DR_ERR_HIP = -4,           /* the HIP runtime reported an error */
+    DR_ERR_NOT_ALIGNED = -5,   /* rows of a zip do not have equal lengths */
+    DR_ERR_DEVICE = -6         /* dr_device_status: the device flagged a fault */
+} dr_status;
+
+typedef enum dr_dtype {
+    DR_I32 = 0,   /* int32 */
+    DR_F32 = 1,   /* IEEE binary32 */
+    DR_BF16 = 2,  /* bfloat16: the upper 16 bits of a binary32 */
+    DR_F64 = 3,   /* IEEE binary64 */
+    DR_I64 = 4    /* int64 */
+} dr_dtype;
+
+/* The transform of the view, applied to the zipped elements x0, x1:
+ * identity x0 (arity 1), square x0*x0 (arity 1), mul x0*x1 (arity 2),
+ * axpy x0 + alpha*x1 (arity 2). For int32 inputs alpha must be an integer. */
+typedef enum dr_op {
+    DR_OP_IDENTITY = 0,
+    DR_OP_SQUARE = 1,
+    DR_OP_MUL = 2,
+    DR_OP_AXPY = 3
+} dr_op;
+
+/* Floating-point accumulation of a reduction. PLAIN: binary32 sums inside a
+ * tile. COMPENSATED: binary32 (sum, error) pairs with error-free
+ * transformations (TwoSum, FMA-based TwoProduct) inside a tile. In both, the
+ * tile partials and the combine across tiles and segments are binary64.
+ * Integer reductions are always exact in int64 and ignore this setting.
+ * binary64 inputs always accumulate in binary64. */
+typedef enum dr_acc {
+    DR_ACC_PLAIN = 0,
+    DR_ACC_COMPENSATED = 1
+} dr_acc;
+
+/* CONCAT: the segments are one distributed range (results: one reduction;
+ * the scan carries across segment boundaries). BATCH: each segment is an
+ * independent range (one reduction per segment; the scan restarts at every
+ * segment). */
+typedef enum dr_mode {
+    DR_MODE_CONCAT = 0,
+    DR_MODE_BATCH = 1
+} dr_mode;
+
+/* Scan flags. REVERSE: suffix sums (element i gets the sum of elements i
+ * and after), the adjoint of the forward scan. CARRY_F32: binary32 carries
+ * for floating-point scans instead of binary64 (only for comparisons of
+ * accuracy; binary64 carries are the default). */
+enum {
+    DR_SCAN_REVERSE = 1u,
+    DR_SCAN_CARRY_F32 = 2u
+};
+
+/* Algorithm ids for dr_workspace_bytes and dr_plan. */
+typedef enum dr_algo {
+    DR_ALGO_FOR_EACH = 0,
+    DR_ALGO_REDUCE = 1,
+    DR_ALGO_SCAN = 2,
+    DR_ALGO_SCAN_REDUCE = 3,
+    DR_ALGO_BROADCAST_MUL = 4
+} dr_algo;
+
+/* The view descriptor: zip arity, element type of the zipped inputs (all
+ * inputs share it), the transform and its scalar. */
+typedef struct dr_view {
+    int32_t arity;     /* 1 or 2; must equal the arity of `op` */
+    int32_t in_dtype;  /* dr_dtype of every zipped input */
+    int32_t op;        /* dr_op */
+    int32_t reserved;  /* must be 0 */
+    double alpha;      /* scalar of DR_OP_AXPY, ignored otherwise */
+} dr_view;
+
+/* One row of the segment table: segment k of every zipped input, the
+ * segment's output stream(s), and its length in elements (the same for all
+ * of them: the zip is aligned, section 4.4 "Zip"). 64 bytes. Pointers are
+ * device pointers; unused slots must be NULL. */
+typedef struct dr_segment {
+    const void* in[DR_MAX_ARITY];
+    void* out[DR_MAX_OUTPUTS];
+    int64_t length;
+    int64_t reserved;   /* must be 0 */
+} dr_segment;
+
+/* The segment table. `rows` is a DEVICE array of n_segments rows read by the
+ * kernels. `host_rows`, when not NULL, is a host copy of the same rows that
+ * the library checks before enqueuing (lengths, NULL pointers, the sum of
+ * lengths, overlap of outputs with inputs); without it only the device
+ * checks apply. total_length must equal the sum of the lengths. */
+typedef struct dr_table {
+    const dr_segment* rows;
+    const dr_segment* host_rows;
+    int64_t n_segments;
+    int64_t total_length;
+    int32_t mode;       /* dr_mode */
+    int32_t reserved;   /* must be 0 */
+} dr_table;
+
+/* Launch shape. block_threads: 256 (the only shape built in this version);
+ * items_per_thread: elements per thread per tile, one of the values
+ * dr_tuning_supported accepts. NULL = the built-in default for the call. */
+typedef struct dr_tuning {
+    int32_t block_threads;
+    int32_t items_per_thread;
+    int32_t reserved0;
+    int32_t reserved1;
+} dr_tuning;
+
+/* Library version (DR_ABI_VERSION). Never fails. */
+int dr_abi_version(void);
+
+/* Static string for a status code. Never fails. */
+const char* dr_status_string(dr_status status);
+
+/* Detail of the last error returned on the calling thread ("" if none). */
+const char* dr_last_error(void);
+
+/* 1 if (algo, view, out_dtype, tuning) has a built kernel, else 0. */
+int dr_tuning_supported(int32_t algo, const dr_view* view, int32_t out_dtype,
+                        const dr_tuning* tuning);
+
+/* Bytes of workspace that `algo` needs for a table of n_segments rows and
+ * total_length elements with this view and tuning (for DR_ALGO_SCAN_REDUCE
+ * the view is the scanned one). Writes *bytes; host only, enqueues nothing. */
+dr_status dr_workspace_bytes(int32_t algo, int64_t n_segments, int64_t total_length,
+                             const dr_view* view, const dr_tuning* tuning, size_t* bytes);
+
+/* Zero-fill a fresh workspace (ws_bytes bytes, 256-byte aligned device
+ * pointer) on `stream`. Needed once after allocation. */
+dr_status dr_workspace_init(void* workspace, size_t ws_bytes, void* stream);
+
+/* Build the tile plan of a large table (more than DR_SMALL_TABLE rows) in
+ * the workspace: the prefix of per-segment tile counts and a tile ->
+ * segment map. Needed once per (table, algo, view dtype, tuning,
+ * workspace); calls whose plan does not match flag a device error and do
+ * nothing. Tables of at most DR_SMALL_TABLE rows need no plan. */
+dr_status dr_plan(const dr_table* table, int32_t algo, const dr_view* view,
+                  const dr_tuning* tuning, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * for_each (section 4.3, "for_each"; section 5.1, "Stream"):
+ * for every segment k and index j < length_k,
+ *     rows[k].out[0][j] = op(in[0][j], in[1][j])
+ * evaluated in the output type with one rounding per arithmetic operation
+ * and no fused multiply-add (the triad a = b + s*c is fl(b + fl(s*c))).
+ * Supported (in_dtype -> out_dtype): F32 -> F32, BF16 -> F32, F64 -> F64,
+ * I32 -> I32 (two's complement wrap), I32 -> I64.
+ * The workspace is needed only for tables larger than DR_SMALL_TABLE
+ * (pass NULL/0 otherwise).
+ */
+dr_status dr_for_each(const dr_table* table, const dr_view* view, int32_t out_dtype,
+                      void* workspace, size_t ws_bytes, const dr_tuning* tuning,
+                      void* stream);
+
+/*
+ * transform_reduce (section 4.3, "reduce"; Algorithms 1 and 3):
+ * R = init + sum of op(in[0][j], in[1][j]) over all elements (CONCAT), or
+ * R_k = init + sum over segment k (BATCH). Partial sums are combined in a
+ * fixed order, so results are the same from run to run.
+ *  - I32 inputs: exact in int64; `init` points to an int64_t (host);
+ *    `result` is a device int64 array.
+ *  - F32/BF16 inputs: per `acc` inside tiles, binary64 across tiles and
+ *    segments; `init` points to a double (host); `result` is a device
+ *    binary64 array. F64 inputs accumulate in binary64.
+ * `result` has 1 (CONCAT) or n_segments (BATCH) elements. An empty range
+ * gives `init`.
+ */
+dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_t acc,
+                              const void* init, void* result, void* workspace,
+                              size_t ws_bytes, const dr_tuning* tuning, void* stream);
+
+/*
+ * inclusive_scan (section 4.3, "inclusive_scan"; Algorithm 4):
+ * out[0] of the element at logical position i receives the sum of the
+ * view over positions 0..i (CONCAT: across segments; BATCH: within the
+ * element's segment), or over positions i.. (DR_SCAN_REVERSE).
+ * The offset of a segment is the total of the segments before it (0 for the
+ * first), reached through a decoupled look-back over tiles in the same
+ * launch. Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
+ * (exact modulo 2^32), F32 -> F32 and BF16 -> F32 (binary32 inside a tile,
+ * binary64 carries unless DR_SCAN_CARRY_F32), F64 -> F64.
+ * In-place (out[0] == in[0], same dtype size) is allowed; other overlap
+ * between outputs and inputs is rejected when host_rows is given.
+ */
+dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t out_dtype,
+                            uint32_t flags, void* workspace, size_t ws_bytes,
+                            const dr_tuning* tuning, void* stream);
+
+/*
+ * Fused inclusive_scan + transform_reduce over the same rows in one launch,
+ * every input element read once: out[0] receives the inclusive scan of the
+ * scan view (identity of in[0]), and `result` the reduction of the reduce
+ * view (op over in[0], in[1]); both per segment in BATCH mode. Types as for
+ * the two calls: F32 in, F32 scan out, binary64 results. `init` is a host
+ * double.
+ */
+dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view,
+                         const dr_view* reduce_view, int32_t acc, const void* init,
+                         void* result, uint32_t flags, void* workspace, size_t ws_bytes,
+                         const dr_tuning* tuning, void* stream);
+
+/*
+ * Adjoint of transform_reduce: for every element, out[w][j] =
+ * fl(g_r * d op / d x_w) for w < `n_grads` outputs, where g is a DEVICE
+ * binary64 array of 1 (CONCAT) or n_segments (BATCH) upstream gradients,
+ * the derivative is evaluated on in[0], in[1] (mul: d/dx0 = x1,
+ * d/dx1 = x0; square: 2*x0; identity: 1; axpy: 1 and alpha), the product is
+ * binary64 and rounded once to the output type (= the input type; BF16
+ * inputs give F32 gradients).
+ */
+dr_status dr_broadcast_mul(const dr_table* table, const dr_view* view, const double* g,
+                           int32_t n_grads, void* workspace, size_t ws_bytes,
+                           const dr_tuning* tuning, void* stream);
+
+/*
+ * Read and clear the device fault flag of a workspace. Synchronises
+ * `stream`. *flags (host) receives the raw flag bits (0 = no fault): 1 = a
+ * row of the device table was malformed (negative length, NULL pointer,
+ * lengths not summing to total_length), 2 = a look-back wait timed out,
+ * 4 = the plan in the workspace did not match the call, 8 = the tile count
+ * exceeded the bound the workspace was sized for. Returns DR_ERR_DEVICE
+ * when any bit was set.
+ */
+dr_status dr_device_status(void* workspace, uint32_t* flags, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DR_H */

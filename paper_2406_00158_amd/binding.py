@@ -1,0 +1,333 @@
+"""Thin ctypes binding of libdr.so (include/dr.h), with the same names.
+
+Argument marshalling only: tensors become device pointers and lengths,
+segment lists become dr_table rows, and every step of the computation runs
+in the HIP kernels behind the C ABI. PyTorch supplies device memory and the
+current stream. If the library is not built this module raises on import
+of the library (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdr.so")
+
+# --- constants mirrored from include/dr.h ------------------------------------
+DR_OK = 0
+DR_I32, DR_F32, DR_BF16, DR_F64, DR_I64 = 0, 1, 2, 3, 4
+DR_OP_IDENTITY, DR_OP_SQUARE, DR_OP_MUL, DR_OP_AXPY = 0, 1, 2, 3
+DR_ACC_PLAIN, DR_ACC_COMPENSATED = 0, 1
+DR_MODE_CONCAT, DR_MODE_BATCH = 0, 1
+DR_SCAN_REVERSE, DR_SCAN_CARRY_F32 = 1, 2
+DR_ALGO_FOR_EACH, DR_ALGO_REDUCE, DR_ALGO_SCAN, DR_ALGO_SCAN_REDUCE, DR_ALGO_BROADCAST_MUL = 0, 1, 2, 3, 4
+DR_SMALL_TABLE = 64
+DR_MAX_ARITY = 4
+DR_MAX_OUTPUTS = 2
+OP_ARITY = {DR_OP_IDENTITY: 1, DR_OP_SQUARE: 1, DR_OP_MUL: 2, DR_OP_AXPY: 2}
+
+TORCH_DTYPE = {DR_I32: torch.int32, DR_F32: torch.float32, DR_BF16: torch.bfloat16,
+               DR_F64: torch.float64, DR_I64: torch.int64}
+DR_DTYPE = {v: k for k, v in TORCH_DTYPE.items()}
+
+OPS = {"identity": DR_OP_IDENTITY, "square": DR_OP_SQUARE, "mul": DR_OP_MUL, "axpy": DR_OP_AXPY}
+ACCS = {"plain": DR_ACC_PLAIN, "compensated": DR_ACC_COMPENSATED}
+MODES = {"concat": DR_MODE_CONCAT, "batch": DR_MODE_BATCH}
+
+
+class dr_view(ctypes.Structure):
+    _fields_ = [("arity", ctypes.c_int32), ("in_dtype", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("alpha", ctypes.c_double)]
+
+
+class dr_segment(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p * DR_MAX_ARITY), ("out", ctypes.c_void_p * DR_MAX_OUTPUTS),
+                ("length", ctypes.c_int64), ("reserved", ctypes.c_int64)]
+
+
+class dr_table(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_void_p), ("host_rows", ctypes.c_void_p),
+                ("n_segments", ctypes.c_int64), ("total_length", ctypes.c_int64),
+                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class dr_tuning(ctypes.Structure):
+    _fields_ = [("block_threads", ctypes.c_int32), ("items_per_thread", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+assert ctypes.sizeof(dr_segment) == 64
+assert ctypes.sizeof(dr_view) == 24
+
+EXPORTS = ["dr_abi_version", "dr_status_string", "dr_last_error", "dr_tuning_supported",
+           "dr_workspace_bytes", "dr_workspace_init", "dr_plan", "dr_for_each",
+           "dr_transform_reduce", "dr_inclusive_scan", "dr_scan_reduce", "dr_broadcast_mul",
+           "dr_device_status"]
+
+_lib = None
+
+
+class DrError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{detail} (status {status})")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libdr.so. Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2406_00158_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P, S = ctypes.c_void_p, ctypes.c_size_t
+    i32, u32, i64 = ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64
+    VP, TP, UP = ctypes.POINTER(dr_view), ctypes.POINTER(dr_table), ctypes.POINTER(dr_tuning)
+    L.dr_abi_version.restype = ctypes.c_int
+    L.dr_status_string.argtypes = [ctypes.c_int]
+    L.dr_status_string.restype = ctypes.c_char_p
+    L.dr_last_error.restype = ctypes.c_char_p
+    L.dr_tuning_supported.argtypes = [i32, VP, i32, UP]
+    L.dr_workspace_bytes.argtypes = [i32, i64, i64, VP, UP, ctypes.POINTER(S)]
+    L.dr_workspace_init.argtypes = [P, S, P]
+    L.dr_plan.argtypes = [TP, i32, VP, UP, P, S, P]
+    L.dr_for_each.argtypes = [TP, VP, i32, P, S, UP, P]
+    L.dr_transform_reduce.argtypes = [TP, VP, i32, P, P, P, S, UP, P]
+    L.dr_inclusive_scan.argtypes = [TP, VP, i32, u32, P, S, UP, P]
+    L.dr_scan_reduce.argtypes = [TP, VP, VP, i32, P, P, u32, P, S, UP, P]
+    L.dr_broadcast_mul.argtypes = [TP, VP, P, i32, P, S, UP, P]
+    L.dr_device_status.argtypes = [P, ctypes.POINTER(u32), P]
+    for name in EXPORTS[3:]:
+        if name not in ("dr_status_string", "dr_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != DR_OK:
+        raise DrError(status, lib().dr_last_error().decode())
+
+
+def _stream(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_view(op: int | str, in_dtype: int | torch.dtype, alpha: float = 0.0) -> dr_view:
+    op = OPS[op] if isinstance(op, str) else op
+    dt = DR_DTYPE[in_dtype] if isinstance(in_dtype, torch.dtype) else in_dtype
+    return dr_view(OP_ARITY[op], dt, op, 0, float(alpha))
+
+
+def make_tuning(items_per_thread: int | None) -> dr_tuning | None:
+    if items_per_thread is None:
+        return None
+    return dr_tuning(256, int(items_per_thread), 0, 0)
+
+
+# --- segment tables -----------------------------------------------------------
+
+@dataclass
+class Table:
+    """A segment table: row k holds segment k of every zipped input and of
+    every output stream, and its length. The tensors are kept alive here."""
+    inputs: list
+    outputs: list
+    mode: int
+    device: torch.device
+    host_rows: ctypes.Array = field(repr=False, default=None)
+    dev_rows: torch.Tensor = field(repr=False, default=None)
+    total_length: int = 0
+
+    @property
+    def n_segments(self) -> int:
+        return len(self.inputs[0]) if self.inputs else 0
+
+    def c_table(self, host_check: bool = True) -> dr_table:
+        rows = self.dev_rows.data_ptr() if self.n_segments else None
+        host = ctypes.addressof(self.host_rows) if (host_check and self.n_segments) else None
+        return dr_table(rows, host, self.n_segments, self.total_length, self.mode, 0)
+
+
+def segments(inputs, outputs=None, mode: int | str = DR_MODE_CONCAT, device=None) -> Table:
+    """Build a table from per-segment tensors.
+
+    inputs:  list over zipped inputs of lists over segments of 1-D tensors
+             (all inputs must have the same number of segments and lengths).
+    outputs: optional list (at most 2) of such lists for output streams.
+    """
+    mode = MODES[mode] if isinstance(mode, str) else mode
+    outputs = outputs or []
+    if not inputs or len(inputs) > DR_MAX_ARITY or len(outputs) > DR_MAX_OUTPUTS:
+        raise ValueError("between 1 and 4 inputs and at most 2 outputs")
+    m = len(inputs[0])
+    for lst in list(inputs) + list(outputs):
+        if len(lst) != m:
+            raise ValueError("every input/output needs the same number of segments")
+    if device is None:
+        first = next((t for t in inputs[0]), None)
+        device = first.device if first is not None else torch.device("cuda")
+    host = (dr_segment * max(1, m))()
+    total = 0
+    for k in range(m):
+        n = inputs[0][k].numel()
+        for lst in list(inputs) + list(outputs):
+            t = lst[k]
+            if t.dim() != 1 or t.numel() != n:
+                raise ValueError(f"segment {k}: every zipped tensor must be 1-D with {n} elements")
+            if not t.is_contiguous():
+                raise ValueError(f"segment {k}: tensors must be contiguous")
+            if t.device != device:
+                raise ValueError(f"segment {k}: tensor on {t.device}, table on {device}")
+        for i, lst in enumerate(inputs):
+            host[k].in_[i] = lst[k].data_ptr() if n else None
+        for i, lst in enumerate(outputs):
+            host[k].out[i] = lst[k].data_ptr() if n else None
+        host[k].length = n
+        total += n
+    raw = np.frombuffer(bytes(host), dtype=np.uint8)[: 64 * m]
+    dev = torch.from_numpy(raw.copy()).to(device) if m else torch.empty(0, dtype=torch.uint8, device=device)
+    return Table(list(inputs), list(outputs), mode, device, host, dev, total)
+
+
+# --- workspace ----------------------------------------------------------------
+
+class Workspace:
+    """A caller-owned device workspace: grown on demand, zero-filled once by
+    dr_workspace_init when (re)allocated, and tracking the plan it holds."""
+
+    def __init__(self, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self.buf = None
+        self.plan_key = None
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr() if self.buf is not None else 0
+
+    @property
+    def nbytes(self) -> int:
+        return self.buf.numel() if self.buf is not None else 0
+
+    def ensure(self, nbytes: int) -> None:
+        if self.buf is not None and self.buf.numel() >= nbytes:
+            return
+        nbytes = max(int(nbytes), 256)
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.buf.data_ptr()) % 256
+        self.buf = self.buf[off: off + nbytes]
+        check(lib().dr_workspace_init(self.ptr, nbytes, _stream(self.device)))
+        self.plan_key = None
+
+    def for_call(self, algo: int, table: Table, view: dr_view, tuning: dr_tuning | None) -> None:
+        size = ctypes.c_size_t(0)
+        tptr = ctypes.byref(tuning) if tuning is not None else None
+        check(lib().dr_workspace_bytes(algo, table.n_segments, table.total_length, ctypes.byref(view),
+                                       tptr, ctypes.byref(size)))
+        self.ensure(size.value)
+        if table.n_segments > DR_SMALL_TABLE:
+            items = tuning.items_per_thread if tuning is not None else 0
+            key = (table.dev_rows.data_ptr(), table.n_segments, table.total_length, view.in_dtype,
+                   algo if algo == DR_ALGO_SCAN_REDUCE else -1, items)
+            if key != self.plan_key:
+                c = table.c_table(host_check=False)
+                check(lib().dr_plan(ctypes.byref(c), algo, ctypes.byref(view), tptr, self.ptr,
+                                    self.nbytes, _stream(self.device)))
+                self.plan_key = key
+
+    def device_status(self) -> int:
+        flags = ctypes.c_uint32(0)
+        st = lib().dr_device_status(self.ptr, ctypes.byref(flags), _stream(self.device))
+        if st not in (DR_OK, -6):
+            check(st)
+        return int(flags.value)
+
+
+_default_ws: dict = {}
+
+
+def default_workspace(device) -> Workspace:
+    device = torch.device(device)
+    key = (device.type, device.index if device.index is not None else torch.cuda.current_device())
+    ws = _default_ws.get(key)
+    if ws is None:
+        ws = _default_ws[key] = Workspace(torch.device("cuda", key[1]))
+    return ws
+
+
+# --- entry points (same names as the C ABI) -----------------------------------
+
+def _tp(tuning):
+    return ctypes.byref(tuning) if tuning is not None else None
+
+
+def dr_for_each(table: Table, view: dr_view, out_dtype: int, workspace: Workspace | None = None,
+                tuning: dr_tuning | None = None, host_check: bool = True) -> None:
+    c = table.c_table(host_check)
+    ws_ptr, ws_n = 0, 0
+    if table.n_segments > DR_SMALL_TABLE:
+        workspace = workspace or default_workspace(table.device)
+        workspace.for_call(DR_ALGO_FOR_EACH, table, view, tuning)
+        ws_ptr, ws_n = workspace.ptr, workspace.nbytes
+    check(lib().dr_for_each(ctypes.byref(c), ctypes.byref(view), out_dtype, ws_ptr or None, ws_n,
+                            _tp(tuning), _stream(table.device)))
+
+
+def dr_transform_reduce(table: Table, view: dr_view, acc: int, init, result: torch.Tensor,
+                        workspace: Workspace | None = None, tuning: dr_tuning | None = None,
+                        host_check: bool = True) -> None:
+    workspace = workspace or default_workspace(table.device)
+    workspace.for_call(DR_ALGO_REDUCE, table, view, tuning)
+    c = table.c_table(host_check)
+    init_c = ctypes.c_int64(int(init)) if view.in_dtype == DR_I32 else ctypes.c_double(float(init))
+    check(lib().dr_transform_reduce(ctypes.byref(c), ctypes.byref(view), acc, ctypes.byref(init_c),
+                                    result.data_ptr() if result.numel() else None, workspace.ptr,
+                                    workspace.nbytes, _tp(tuning), _stream(table.device)))
+
+
+def dr_inclusive_scan(table: Table, view: dr_view, out_dtype: int, flags: int = 0,
+                      workspace: Workspace | None = None, tuning: dr_tuning | None = None,
+                      host_check: bool = True) -> None:
+    workspace = workspace or default_workspace(table.device)
+    workspace.for_call(DR_ALGO_SCAN, table, view, tuning)
+    c = table.c_table(host_check)
+    check(lib().dr_inclusive_scan(ctypes.byref(c), ctypes.byref(view), out_dtype, flags, workspace.ptr,
+                                  workspace.nbytes, _tp(tuning), _stream(table.device)))
+
+
+def dr_scan_reduce(table: Table, scan_view: dr_view, reduce_view: dr_view, acc: int, init: float,
+                   result: torch.Tensor, flags: int = 0, workspace: Workspace | None = None,
+                   tuning: dr_tuning | None = None, host_check: bool = True) -> None:
+    workspace = workspace or default_workspace(table.device)
+    workspace.for_call(DR_ALGO_SCAN_REDUCE, table, scan_view, tuning)
+    c = table.c_table(host_check)
+    init_c = ctypes.c_double(float(init))
+    check(lib().dr_scan_reduce(ctypes.byref(c), ctypes.byref(scan_view), ctypes.byref(reduce_view), acc,
+                               ctypes.byref(init_c), result.data_ptr() if result.numel() else None, flags,
+                               workspace.ptr, workspace.nbytes, _tp(tuning), _stream(table.device)))
+
+
+def dr_broadcast_mul(table: Table, view: dr_view, g: torch.Tensor, n_grads: int,
+                     workspace: Workspace | None = None, tuning: dr_tuning | None = None,
+                     host_check: bool = True) -> None:
+    if g.dtype != torch.float64 or not g.is_contiguous():
+        raise TypeError("g must be a contiguous float64 device tensor")
+    c = table.c_table(host_check)
+    ws_ptr, ws_n = 0, 0
+    if table.n_segments > DR_SMALL_TABLE:
+        workspace = workspace or default_workspace(table.device)
+        workspace.for_call(DR_ALGO_BROADCAST_MUL, table, view, tuning)
+        ws_ptr, ws_n = workspace.ptr, workspace.nbytes
+    check(lib().dr_broadcast_mul(ctypes.byref(c), ctypes.byref(view), g.data_ptr(), n_grads,
+                                 ws_ptr or None, ws_n, _tp(tuning), _stream(table.device)))
+
+
+def dr_device_status(workspace: Workspace) -> int:
+    """Raw device fault flags of the workspace (0 = none); clears them."""
+    return workspace.device_status()

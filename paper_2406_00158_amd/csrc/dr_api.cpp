@@ -1,0 +1,485 @@
+// dr_api.cpp — host side of the C ABI declared in include/dr.h: argument
+// checks, workspace layout, kernel selection and launch. Every entry point
+// checks everything it can on the host before enqueuing anything, and
+// returns a dr_status; nothing throws across the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dr.h"
+#include "dr_internal.hpp"
+
+namespace {
+
+using namespace dr;
+
+thread_local std::string g_err;
+
+dr_status fail(dr_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+dr_status ok() {
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status hip_fail(hipError_t e, const char* what) {
+    return fail(DR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int dtype_size(int dt) {
+    switch (dt) {
+    case DR_I32: return 4;
+    case DR_F32: return 4;
+    case DR_BF16: return 2;
+    case DR_F64: return 8;
+    case DR_I64: return 8;
+    default: return 0;
+    }
+}
+
+int op_arity(int op) {
+    switch (op) {
+    case DR_OP_IDENTITY: return 1;
+    case DR_OP_SQUARE: return 1;
+    case DR_OP_MUL: return 2;
+    case DR_OP_AXPY: return 2;
+    default: return 0;
+    }
+}
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+int default_items(int algo, int in_dt) {
+    (void)algo;
+    (void)in_dt;
+    return 16;
+}
+
+// Bound of the wait loops, in wall-clock ticks (about 2.7 s at 100 MHz);
+// DR_SPIN_TICKS overrides it (tests of the timeout path).
+uint64_t spin_ticks() {
+    static uint64_t v = [] {
+        const char* e = std::getenv("DR_SPIN_TICKS");
+        if (e && *e) return (uint64_t)std::strtoull(e, nullptr, 10);
+        return (uint64_t)1 << 28;
+    }();
+    return v;
+}
+
+dr_status check_view(const dr_view* v, bool int_ok) {
+    if (!v) return fail(DR_ERR_INVALID_ARG, "view is NULL");
+    if (v->reserved != 0) return fail(DR_ERR_INVALID_ARG, "view.reserved must be 0");
+    const int ar = op_arity(v->op);
+    if (ar == 0) return fail(DR_ERR_INVALID_ARG, "unknown op %d", (int)v->op);
+    if (v->arity != ar)
+        return fail(DR_ERR_INVALID_ARG, "view arity %d does not match op %d (arity %d)", (int)v->arity,
+                    (int)v->op, ar);
+    if (v->in_dtype != DR_I32 && v->in_dtype != DR_F32 && v->in_dtype != DR_BF16 && v->in_dtype != DR_F64)
+        return fail(DR_ERR_UNSUPPORTED, "input dtype %d is not supported", (int)v->in_dtype);
+    if (v->in_dtype == DR_I32) {
+        if (!int_ok) return fail(DR_ERR_UNSUPPORTED, "int32 inputs are not supported by this call");
+        if (v->op == DR_OP_AXPY && (v->alpha != std::floor(v->alpha) || std::fabs(v->alpha) > 2147483647.0))
+            return fail(DR_ERR_INVALID_ARG, "int32 axpy needs an integer alpha");
+    }
+    if (!std::isfinite(v->alpha) && v->op == DR_OP_AXPY)
+        return fail(DR_ERR_INVALID_ARG, "alpha must be finite");
+    return DR_OK;
+}
+
+dr_status check_table(const dr_table* t) {
+    if (!t) return fail(DR_ERR_INVALID_ARG, "table is NULL");
+    if (t->reserved != 0) return fail(DR_ERR_INVALID_ARG, "table.reserved must be 0");
+    if (t->n_segments < 0) return fail(DR_ERR_INVALID_ARG, "n_segments < 0");
+    if (t->n_segments > INT32_MAX) return fail(DR_ERR_UNSUPPORTED, "more than 2^31-1 segments");
+    if (t->total_length < 0) return fail(DR_ERR_INVALID_ARG, "total_length < 0");
+    if (t->total_length >= ((int64_t)1 << 40)) return fail(DR_ERR_UNSUPPORTED, "total_length >= 2^40");
+    if (t->mode != DR_MODE_CONCAT && t->mode != DR_MODE_BATCH)
+        return fail(DR_ERR_INVALID_ARG, "unknown mode %d", (int)t->mode);
+    if (t->n_segments > 0 && !t->rows) return fail(DR_ERR_INVALID_ARG, "rows is NULL");
+    return DR_OK;
+}
+
+struct Interval {
+    uintptr_t lo, hi;   // [lo, hi)
+    int64_t row;
+    int kind;           // 0 input, 1 output
+};
+
+// Host mirror checks: lengths, NULLs, element alignment, sum, overlap.
+dr_status check_host_rows(const dr_table* t, int arity, int nout, int ies, int oes, bool inplace_ok) {
+    const dr_segment* r = t->host_rows;
+    if (!r) return DR_OK;
+    int64_t sum = 0;
+    std::vector<Interval> iv;
+    iv.reserve((size_t)t->n_segments * (arity + nout));
+    for (int64_t k = 0; k < t->n_segments; ++k) {
+        const dr_segment& s = r[k];
+        if (s.reserved != 0) return fail(DR_ERR_INVALID_ARG, "row %lld: reserved must be 0", (long long)k);
+        if (s.length < 0) return fail(DR_ERR_INVALID_ARG, "row %lld: negative length", (long long)k);
+        sum += s.length;
+        if (s.length == 0) continue;
+        for (int i = 0; i < arity; ++i) {
+            if (!s.in[i]) return fail(DR_ERR_INVALID_ARG, "row %lld: in[%d] is NULL", (long long)k, i);
+            if ((uintptr_t)s.in[i] % ies)
+                return fail(DR_ERR_INVALID_ARG, "row %lld: in[%d] is not aligned to its element size",
+                            (long long)k, i);
+            iv.push_back({(uintptr_t)s.in[i], (uintptr_t)s.in[i] + (uintptr_t)s.length * ies, k, 0});
+        }
+        for (int i = 0; i < nout; ++i) {
+            if (!s.out[i]) return fail(DR_ERR_INVALID_ARG, "row %lld: out[%d] is NULL", (long long)k, i);
+            if ((uintptr_t)s.out[i] % oes)
+                return fail(DR_ERR_INVALID_ARG, "row %lld: out[%d] is not aligned to its element size",
+                            (long long)k, i);
+            iv.push_back({(uintptr_t)s.out[i], (uintptr_t)s.out[i] + (uintptr_t)s.length * oes, k, 1});
+        }
+    }
+    if (sum != t->total_length)
+        return fail(DR_ERR_INVALID_ARG, "total_length %lld != sum of lengths %lld",
+                    (long long)t->total_length, (long long)sum);
+    if (nout == 0) return DR_OK;
+    // an output may coincide exactly with an input of its own row (in place,
+    // same element size); any other overlap that involves an output is an error
+    std::sort(iv.begin(), iv.end(), [](const Interval& a, const Interval& b) { return a.lo < b.lo; });
+    for (size_t i = 0; i < iv.size(); ++i) {
+        for (size_t j = i + 1; j < iv.size() && iv[j].lo < iv[i].hi; ++j) {
+            const Interval &a = iv[i], &b = iv[j];
+            if (a.kind == 0 && b.kind == 0) continue;   // inputs may overlap each other
+            const bool same = a.lo == b.lo && a.hi == b.hi && a.row == b.row && a.kind != b.kind;
+            if (same && inplace_ok && ies == oes) continue;
+            return fail(DR_ERR_INVALID_ARG, "row %lld: an output overlaps %s of row %lld",
+                        (long long)(a.kind ? a.row : b.row), (a.kind && b.kind) ? "an output" : "an input",
+                        (long long)(a.kind ? b.row : a.row));
+        }
+    }
+    return DR_OK;
+}
+
+dr_status resolve_items(const dr_tuning* tu, int algo, int in_dt, int& items) {
+    items = default_items(algo, in_dt);
+    if (!tu) return DR_OK;
+    if (tu->reserved0 || tu->reserved1) return fail(DR_ERR_INVALID_ARG, "tuning.reserved must be 0");
+    if (tu->block_threads != 0 && tu->block_threads != kBlock)
+        return fail(DR_ERR_UNSUPPORTED, "block_threads must be %d", kBlock);
+    if (tu->items_per_thread != 0) items = tu->items_per_thread;
+    return DR_OK;
+}
+
+int64_t tmax_for(int64_t m, int64_t total, int64_t tile, int ies) {
+    const int V = 16 / ies;
+    const int64_t t = (total + m * (int64_t)(V - 1) + tile - 1) / tile + m;
+    return t < 1 ? 1 : t;
+}
+
+bool uses_combine(int algo) { return algo == DR_ALGO_REDUCE || algo == DR_ALGO_SCAN_REDUCE; }
+
+WsLayout layout_for(int algo, int64_t m, int64_t tmax) {
+    WsLayout L{};
+    uint64_t off = kFixedBytes;
+    L.off_plan_first = off;
+    if (m > DR_SMALL_TABLE) off += align256((uint64_t)(m + 1) * 8);
+    L.off_plan_tseg = off;
+    if (m > DR_SMALL_TABLE) off += align256((uint64_t)tmax * 8);
+    L.tile_words = algo == DR_ALGO_REDUCE ? 2 : algo == DR_ALGO_SCAN ? 4 : algo == DR_ALGO_SCAN_REDUCE ? 6 : 0;
+    L.part_word = algo == DR_ALGO_REDUCE ? 0 : 4;
+    L.off_tile = off;
+    off += align256((uint64_t)tmax * L.tile_words * 8);
+    const uint64_t ngroups = uses_combine(algo) ? (uint64_t)(tmax / kGroupTiles + m + 2) : 0;
+    L.off_gcnt = off;
+    off += align256(ngroups * 8);
+    L.off_gpart = off;
+    off += align256(ngroups * 16);
+    const uint64_t nunits = uses_combine(algo) ? (uint64_t)std::max<int64_t>(m, 1) : 0;
+    L.off_ucnt = off;
+    off += align256(nunits * 8);
+    L.bytes = off;
+    return L;
+}
+
+// Everything a launch needs besides the kernel.
+struct Prepared {
+    LaunchArgs a;
+    int64_t grid;
+};
+
+dr_status prepare(const dr_table* t, int algo, int in_dt, int out_dt, int arity, int nout,
+                  const dr_tuning* tu, void* ws, size_t ws_bytes, bool ws_required, bool inplace_ok,
+                  Prepared& p, int& items) {
+    dr_status s = check_table(t);
+    if (s) return s;
+    const int ies = dtype_size(in_dt);
+    const int oes = nout > 0 ? dtype_size(out_dt) : 0;
+    s = check_host_rows(t, arity, nout, ies, oes, inplace_ok);
+    if (s) return s;
+    s = resolve_items(tu, algo, in_dt, items);
+    if (s) return s;
+    const int V = 16 / ies;
+    if (items <= 0 || items % V != 0) return fail(DR_ERR_UNSUPPORTED, "items_per_thread %d", items);
+    const int64_t tile = (int64_t)kBlock * items;
+    const int64_t tmax = tmax_for(t->n_segments, t->total_length, tile, ies);
+    if (tmax >= ((int64_t)1 << 31)) return fail(DR_ERR_UNSUPPORTED, "too many tiles (%lld)", (long long)tmax);
+    const WsLayout lay = layout_for(algo, t->n_segments, tmax);
+    const bool need_ws = ws_required || t->n_segments > DR_SMALL_TABLE;
+    if (need_ws) {
+        if (!ws) return fail(DR_ERR_WORKSPACE, "a workspace is required");
+        if ((uintptr_t)ws % 256) return fail(DR_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+        if (ws_bytes < lay.bytes)
+            return fail(DR_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %llu needed", ws_bytes,
+                        (unsigned long long)lay.bytes);
+    }
+    LaunchArgs& a = p.a;
+    std::memset(&a, 0, sizeof a);
+    a.rows = t->rows;
+    a.m = t->n_segments;
+    a.total = t->total_length;
+    a.tile = tile;
+    a.tmax = tmax;
+    a.ies = ies;
+    a.oes = oes;
+    a.mode = t->mode;
+    a.arity = arity;
+    a.nout = nout;
+    a.ws = (uint8_t*)ws;
+    a.lay = lay;
+    a.spin_ticks = spin_ticks();
+    p.grid = tmax;
+    return DR_OK;
+}
+
+dr_status launch(LaunchFn fn, const Prepared& p, void* stream, const char* what) {
+    hipError_t e = fn(p.a, p.grid, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, what);
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int dr_abi_version(void) { return DR_ABI_VERSION; }
+
+const char* dr_status_string(dr_status s) {
+    switch (s) {
+    case DR_OK: return "ok";
+    case DR_ERR_INVALID_ARG: return "invalid argument";
+    case DR_ERR_UNSUPPORTED: return "unsupported combination";
+    case DR_ERR_WORKSPACE: return "workspace missing or too small";
+    case DR_ERR_HIP: return "HIP runtime error";
+    case DR_ERR_NOT_ALIGNED: return "zip inputs are not aligned";
+    case DR_ERR_DEVICE: return "device-side fault flagged";
+    default: return "unknown status";
+    }
+}
+
+const char* dr_last_error(void) { return g_err.c_str(); }
+
+int dr_tuning_supported(int32_t algo, const dr_view* v, int32_t out_dtype, const dr_tuning* tu) {
+    if (!v) return 0;
+    int items = 0;
+    if (resolve_items(tu, algo, v->in_dtype, items) != DR_OK) return 0;
+    switch (algo) {
+    case DR_ALGO_FOR_EACH: return find_for_each(v->in_dtype, out_dtype, v->op, items) != nullptr;
+    case DR_ALGO_REDUCE:
+        return find_reduce(v->in_dtype, v->op, out_dtype /* acc */, items) != nullptr;
+    case DR_ALGO_SCAN:
+        return find_scan(v->in_dtype, out_dtype, v->op, true, items) != nullptr;
+    case DR_ALGO_SCAN_REDUCE: return find_scan_reduce(v->in_dtype, DR_OP_MUL, DR_ACC_COMPENSATED, items) != nullptr;
+    case DR_ALGO_BROADCAST_MUL: return find_broadcast_mul(v->in_dtype, v->op, items) != nullptr;
+    default: return 0;
+    }
+}
+
+dr_status dr_workspace_bytes(int32_t algo, int64_t n_segments, int64_t total_length, const dr_view* view,
+                             const dr_tuning* tuning, size_t* bytes) {
+    if (!bytes) return fail(DR_ERR_INVALID_ARG, "bytes is NULL");
+    if (!view) return fail(DR_ERR_INVALID_ARG, "view is NULL");
+    if (algo < DR_ALGO_FOR_EACH || algo > DR_ALGO_BROADCAST_MUL) return fail(DR_ERR_INVALID_ARG, "unknown algo");
+    if (n_segments < 0 || total_length < 0) return fail(DR_ERR_INVALID_ARG, "negative size");
+    const int ies = dtype_size(view->in_dtype);
+    if (ies == 0) return fail(DR_ERR_UNSUPPORTED, "input dtype %d", (int)view->in_dtype);
+    int items = 0;
+    dr_status s = resolve_items(tuning, algo, view->in_dtype, items);
+    if (s) return s;
+    if (items <= 0 || items % (16 / ies)) return fail(DR_ERR_UNSUPPORTED, "items_per_thread %d", items);
+    const int64_t tmax = tmax_for(n_segments, total_length, (int64_t)kBlock * items, ies);
+    *bytes = (size_t)layout_for(algo, n_segments, tmax).bytes;
+    return ok();
+}
+
+dr_status dr_workspace_init(void* ws, size_t ws_bytes, void* stream) {
+    if (!ws) return fail(DR_ERR_WORKSPACE, "workspace is NULL");
+    if ((uintptr_t)ws % 256) return fail(DR_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < kFixedBytes) return fail(DR_ERR_WORKSPACE, "workspace smaller than its fixed part");
+    hipError_t e = launch_zero(ws, ws_bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "workspace init");
+    return ok();
+}
+
+dr_status dr_plan(const dr_table* table, int32_t algo, const dr_view* view, const dr_tuning* tuning, void* ws,
+                  size_t ws_bytes, void* stream) {
+    dr_status s = check_view(view, true);
+    if (s) return s;
+    if (algo < DR_ALGO_FOR_EACH || algo > DR_ALGO_BROADCAST_MUL) return fail(DR_ERR_INVALID_ARG, "unknown algo");
+    Prepared p;
+    int items;
+    const int arity = algo == DR_ALGO_SCAN_REDUCE ? 2 : view->arity;
+    s = prepare(table, algo, view->in_dtype, view->in_dtype, arity, 0, tuning, ws, ws_bytes, true, false, p,
+                items);
+    if (s) return s;
+    if (table->n_segments <= DR_SMALL_TABLE) return ok();   // planned inside every launch
+    hipError_t e = launch_plan(p.a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "plan");
+    return ok();
+}
+
+dr_status dr_for_each(const dr_table* table, const dr_view* view, int32_t out_dtype, void* ws, size_t ws_bytes,
+                      const dr_tuning* tuning, void* stream) {
+    dr_status s = check_view(view, true);
+    if (s) return s;
+    const int in = view->in_dtype;
+    const bool okpair = (in == DR_F32 && out_dtype == DR_F32) || (in == DR_BF16 && out_dtype == DR_F32) ||
+                        (in == DR_F64 && out_dtype == DR_F64) || (in == DR_I32 && out_dtype == DR_I32) ||
+                        (in == DR_I32 && out_dtype == DR_I64);
+    if (!okpair) return fail(DR_ERR_UNSUPPORTED, "for_each %d -> %d is not supported", in, (int)out_dtype);
+    Prepared p;
+    int items;
+    s = prepare(table, DR_ALGO_FOR_EACH, in, out_dtype, view->arity, 1, tuning, ws, ws_bytes, false, true, p,
+                items);
+    if (s) return s;
+    LaunchFn fn = find_for_each(in, out_dtype, view->op, items);
+    if (!fn) return fail(DR_ERR_UNSUPPORTED, "for_each kernel not built for items_per_thread %d", items);
+    p.a.alpha = view->alpha;
+    return launch(fn, p, stream, "for_each launch");
+}
+
+dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_t acc, const void* init,
+                              void* result, void* ws, size_t ws_bytes, const dr_tuning* tuning, void* stream) {
+    dr_status s = check_view(view, true);
+    if (s) return s;
+    if (acc != DR_ACC_PLAIN && acc != DR_ACC_COMPENSATED) return fail(DR_ERR_INVALID_ARG, "unknown acc %d", acc);
+    if (!init) return fail(DR_ERR_INVALID_ARG, "init is NULL");
+    if (!result && !(table && table->mode == DR_MODE_BATCH && table->n_segments == 0))
+        return fail(DR_ERR_INVALID_ARG, "result is NULL");
+    Prepared p;
+    int items;
+    s = prepare(table, DR_ALGO_REDUCE, view->in_dtype, 0, view->arity, 0, tuning, ws, ws_bytes, true, false, p,
+                items);
+    if (s) return s;
+    LaunchFn fn = find_reduce(view->in_dtype, view->op, acc, items);
+    if (!fn) return fail(DR_ERR_UNSUPPORTED, "reduce kernel not built for items_per_thread %d", items);
+    p.a.alpha = view->alpha;
+    p.a.result = result;
+    if (view->in_dtype == DR_I32) p.a.init_i = *(const int64_t*)init;
+    else p.a.init_f = *(const double*)init;
+    return launch(fn, p, stream, "transform_reduce launch");
+}
+
+dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t out_dtype, uint32_t flags,
+                            void* ws, size_t ws_bytes, const dr_tuning* tuning, void* stream) {
+    dr_status s = check_view(view, true);
+    if (s) return s;
+    const int in = view->in_dtype;
+    const bool okpair = (in == DR_I32 && (out_dtype == DR_I64 || out_dtype == DR_I32)) ||
+                        (in == DR_F32 && out_dtype == DR_F32) || (in == DR_BF16 && out_dtype == DR_F32) ||
+                        (in == DR_F64 && out_dtype == DR_F64);
+    if (!okpair) return fail(DR_ERR_UNSUPPORTED, "inclusive_scan %d -> %d is not supported", in, (int)out_dtype);
+    if (flags & ~(uint32_t)(DR_SCAN_REVERSE | DR_SCAN_CARRY_F32))
+        return fail(DR_ERR_INVALID_ARG, "unknown scan flags 0x%x", flags);
+    if ((flags & DR_SCAN_CARRY_F32) && in != DR_F32 && in != DR_BF16)
+        return fail(DR_ERR_INVALID_ARG, "DR_SCAN_CARRY_F32 applies to binary32/bfloat16 inputs only");
+    Prepared p;
+    int items;
+    s = prepare(table, DR_ALGO_SCAN, in, out_dtype, view->arity, 1, tuning, ws, ws_bytes, true,
+                view->op == DR_OP_IDENTITY, p, items);
+    if (s) return s;
+    LaunchFn fn = find_scan(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items);
+    if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
+    p.a.alpha = view->alpha;
+    p.a.flags = flags;
+    return launch(fn, p, stream, "inclusive_scan launch");
+}
+
+dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view, const dr_view* reduce_view,
+                         int32_t acc, const void* init, void* result, uint32_t flags, void* ws, size_t ws_bytes,
+                         const dr_tuning* tuning, void* stream) {
+    dr_status s = check_view(scan_view, false);
+    if (s) return s;
+    s = check_view(reduce_view, false);
+    if (s) return s;
+    if (scan_view->op != DR_OP_IDENTITY || scan_view->in_dtype != DR_F32)
+        return fail(DR_ERR_UNSUPPORTED, "fused scan: the scan view must be identity over binary32 in[0]");
+    if (reduce_view->in_dtype != DR_F32 || reduce_view->op != DR_OP_MUL)
+        return fail(DR_ERR_UNSUPPORTED, "fused scan: the reduce view must be mul over binary32 in[0], in[1]");
+    if (acc != DR_ACC_PLAIN && acc != DR_ACC_COMPENSATED) return fail(DR_ERR_INVALID_ARG, "unknown acc %d", acc);
+    if (flags & ~(uint32_t)DR_SCAN_REVERSE) return fail(DR_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (!init) return fail(DR_ERR_INVALID_ARG, "init is NULL");
+    if (!result && !(table && table->mode == DR_MODE_BATCH && table->n_segments == 0))
+        return fail(DR_ERR_INVALID_ARG, "result is NULL");
+    Prepared p;
+    int items;
+    s = prepare(table, DR_ALGO_SCAN_REDUCE, DR_F32, DR_F32, 2, 1, tuning, ws, ws_bytes, true, true, p, items);
+    if (s) return s;
+    LaunchFn fn = find_scan_reduce(DR_F32, reduce_view->op, acc, items);
+    if (!fn) return fail(DR_ERR_UNSUPPORTED, "fused scan kernel not built for this combination");
+    p.a.flags = flags;
+    p.a.result = result;
+    p.a.init_f = *(const double*)init;
+    return launch(fn, p, stream, "scan_reduce launch");
+}
+
+dr_status dr_broadcast_mul(const dr_table* table, const dr_view* view, const double* g, int32_t n_grads,
+                           void* ws, size_t ws_bytes, const dr_tuning* tuning, void* stream) {
+    dr_status s = check_view(view, false);
+    if (s) return s;
+    if (!g) return fail(DR_ERR_INVALID_ARG, "g is NULL");
+    if (n_grads < 1 || n_grads > view->arity)
+        return fail(DR_ERR_INVALID_ARG, "n_grads must be 1..%d", (int)view->arity);
+    const int in = view->in_dtype;
+    const int out = in == DR_F64 ? DR_F64 : DR_F32;
+    Prepared p;
+    int items;
+    s = prepare(table, DR_ALGO_BROADCAST_MUL, in, out, view->arity, n_grads, tuning, ws, ws_bytes, false, false,
+                p, items);
+    if (s) return s;
+    LaunchFn fn = find_broadcast_mul(in, view->op, items);
+    if (!fn) return fail(DR_ERR_UNSUPPORTED, "broadcast_mul kernel not built for this combination");
+    p.a.alpha = view->alpha;
+    p.a.g = g;
+    return launch(fn, p, stream, "broadcast_mul launch");
+}
+
+dr_status dr_device_status(void* ws, uint32_t* flags, void* stream) {
+    if (!ws) return fail(DR_ERR_WORKSPACE, "workspace is NULL");
+    if (!flags) return fail(DR_ERR_INVALID_ARG, "flags is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t host = 0;
+    void* dev = (char*)ws + offsetof(Header, error);
+    hipError_t e = hipMemcpyAsync(&host, dev, sizeof host, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "device status read");
+    *flags = host;
+    if (host != 0) {
+        const uint32_t zero = 0;
+        e = hipMemcpyAsync(dev, &zero, sizeof zero, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "device status clear");
+        return fail(DR_ERR_DEVICE, "device fault flags 0x%x", host);
+    }
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// dr_combine.hpp — deterministic combine of partial sums into the result(s)
+// of a reduction, inside the launch that produced them.
+//
+// The paper's reduce computes a partial per segment and adds the partials
+// once all are complete (section 4.3, "reduce"; Algorithm 3). Here a
+// "unit" is what one result covers: one segment's tiles (BATCH), or the
+// workgroups of the launch, each holding the sum of its own tiles (CONCAT).
+// Each member publishes its partial; the last member to arrive in a group of
+// 64 consecutive members sums the group's partials, and the last group to
+// arrive sums the group sums and adds `init`. Arrivals are counted with
+// tagged agent-scope counters, but the sums always run in member order over
+// a fixed tree, so a result does not depend on the order in which
+// workgroups happen to finish. Everything is tagged with the launch epoch,
+// so nothing needs clearing before the next launch.
+#pragma once
+
+#include <type_traits>
+
+#include "dr_device.hpp"
+
+namespace dr {
+
+template <class P>
+__device__ __forceinline__ void write_result(const LaunchArgs& a, int64_t unit, P sum) {
+    if constexpr (!std::is_floating_point<P>::value) {
+        ((int64_t*)a.result)[unit] = a.init_i + (int64_t)sum;
+    } else {
+        ((double*)a.result)[unit] = a.init_f + (double)sum;
+    }
+}
+
+template <class P>
+__device__ __forceinline__ P wait_tagged(const LaunchArgs& a, const uint64_t* w, uint32_t tag) {
+    uint64_t bitsv = 0;
+    if (!tagged_load(w, tag, bitsv)) {
+        Deadline dl(a.spin_ticks);
+        while (!tagged_load(w, tag, bitsv)) {
+            if (dl.passed()) {
+                flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
+                bitsv = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return from_bits<P>(bitsv);
+}
+
+// Results of the empty BATCH segments that follow segment k (k = -1: the
+// leading ones) are `init`: written by the workgroup of the first tile of
+// the preceding non-empty segment. Thread 0 only.
+template <class P>
+__device__ __forceinline__ void fill_empty_after(const LaunchArgs& a, int64_t k) {
+    for (int64_t kk = k + 1; kk < a.m && a.rows[kk].length == 0; ++kk) write_result<P>(a, kk, (P)0);
+}
+
+// Member `idx` (0-based within its unit of `count` members, whose partial
+// words start at member slot `base` of the tile-word array) publishes
+// `partial` (held by thread 0) and, if it completes its group or the unit,
+// combines. `slot0` is the unit's first group slot. Whole workgroup.
+template <class P>
+__device__ __forceinline__ void combine_member(const LaunchArgs& a, uint32_t tag, int64_t unit, int64_t base,
+                                               int64_t idx, int64_t count, int64_t slot0, P partial) {
+    __shared__ int s_last;
+    const int64_t gi = idx / kGroupTiles;
+    const int64_t g0 = gi * kGroupTiles;
+    const int64_t gn = (count - g0) < kGroupTiles ? (count - g0) : kGroupTiles;
+    const int64_t ngroups = (count + kGroupTiles - 1) / kGroupTiles;
+    uint64_t* tw = (uint64_t*)(a.ws + a.lay.off_tile);
+    uint64_t* gcnt = (uint64_t*)(a.ws + a.lay.off_gcnt);
+    uint64_t* gpart = (uint64_t*)(a.ws + a.lay.off_gpart);
+    uint64_t* ucnt = (uint64_t*)(a.ws + a.lay.off_ucnt);
+    const int64_t TW = a.lay.tile_words, PW = a.lay.part_word;
+
+    if (threadIdx.x == 0) {
+        tagged_store(tw + (base + idx) * TW + PW, tag, to_bits(partial));
+        s_last = tagged_count(gcnt + slot0 + gi, tag) == (uint32_t)(gn - 1);
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x < 64) {
+        // wave 0: sum the group's partials in member order
+        const int l = lane_id();
+        P v = (P)0;
+        if (l < gn) v = wait_tagged<P>(a, tw + (base + g0 + l) * TW + PW, tag);
+        const P gsum = wave_sum(v);
+        if (ngroups == 1) {
+            if (l == 0) write_result<P>(a, unit, gsum);
+        } else {
+            int last = 0;
+            if (l == 0) {
+                tagged_store(gpart + (slot0 + gi) * 2, tag, to_bits(gsum));
+                last = tagged_count(ucnt + unit, tag) == (uint32_t)(ngroups - 1);
+            }
+            last = readlane(last, 0);
+            if (last) {
+                P acc = (P)0;
+                for (int64_t g = l; g < ngroups; g += 64) acc += wait_tagged<P>(a, gpart + (slot0 + g) * 2, tag);
+                const P tot = wave_sum(acc);
+                if (l == 0) write_result<P>(a, unit, tot);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// BATCH: tile t of segment si publishes its partial; the segment's last
+// group writes result[k]. Group slots of segment k start at first/64 + k.
+template <class P>
+__device__ __forceinline__ void combine_tile_batch(const LaunchArgs& a, uint32_t tag, int64_t t,
+                                                   const SegInfo& si, P partial) {
+    if (threadIdx.x == 0 && t == si.first) {
+        if (t == 0) fill_empty_after<P>(a, -1);
+        fill_empty_after<P>(a, si.k);
+    }
+    combine_member<P>(a, tag, si.k, si.first, t - si.first, si.ntiles, si.first / kGroupTiles + si.k, partial);
+}
+
+// CONCAT: every workgroup publishes the sum of its tiles; result[0].
+template <class P>
+__device__ __forceinline__ void combine_grid(const LaunchArgs& a, uint32_t tag, P partial) {
+    combine_member<P>(a, tag, 0, 0, blockIdx.x, gridDim.x, 0, partial);
+}
+
+// BATCH launch with no tiles at all: every result is `init`.
+template <class P>
+__device__ __forceinline__ void write_all_init(const LaunchArgs& a) {
+    for (int64_t k = 0; k < a.m; ++k) write_result<P>(a, k, (P)0);
+}
+
+}  // namespace dr

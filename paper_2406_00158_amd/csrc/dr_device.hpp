@@ -1,0 +1,520 @@
+// dr_device.hpp — device-side building blocks shared by the gfx950 kernels:
+// element types and 16-byte vector access, the view transforms, wave64
+// scans/reductions on DPP, epoch-tagged status words for cross-workgroup
+// communication, and the segment/tile geometry of a launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dr.h"
+#include "dr_internal.hpp"
+
+namespace dr {
+
+// ---------------------------------------------------------------------------
+// Element types
+// ---------------------------------------------------------------------------
+
+struct bf16_t { uint16_t bits; };
+
+template <int DT> struct elem;
+template <> struct elem<DR_I32> { using T = int32_t; using acc = int64_t; };
+template <> struct elem<DR_F32> { using T = float; using acc = float; };
+template <> struct elem<DR_BF16> { using T = uint16_t; using acc = float; };
+template <> struct elem<DR_F64> { using T = double; using acc = double; };
+template <> struct elem<DR_I64> { using T = int64_t; using acc = int64_t; };
+
+template <int DT> constexpr int esize() { return (int)sizeof(typename elem<DT>::T); }
+template <int DT> constexpr int vwidth() { return 16 / esize<DT>(); }   // elements per 16 B
+
+// Exact decode of one stored element into the arithmetic type of the view:
+// bfloat16 is the upper half of a binary32 pattern.
+__device__ __forceinline__ float bf16_decode(uint16_t b) {
+    return __uint_as_float(((uint32_t)b) << 16);
+}
+
+template <int DT> __device__ __forceinline__ typename elem<DT>::acc decode(typename elem<DT>::T v);
+template <> __device__ __forceinline__ int64_t decode<DR_I32>(int32_t v) { return (int64_t)v; }
+template <> __device__ __forceinline__ float decode<DR_F32>(float v) { return v; }
+template <> __device__ __forceinline__ float decode<DR_BF16>(uint16_t v) { return bf16_decode(v); }
+template <> __device__ __forceinline__ double decode<DR_F64>(double v) { return v; }
+
+// 16-byte vector of V elements, accessed as 4 dwords.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int DT>
+struct vec {
+    typename elem<DT>::T e[vwidth<DT>()];
+};
+
+template <int DT>
+__device__ __forceinline__ vec<DT> load_vec(const void* base, int64_t j) {
+    const u32x4* p = (const u32x4*)((const char*)base + j * esize<DT>());
+    u32x4 w = __builtin_nontemporal_load(p);
+    vec<DT> v;
+    __builtin_memcpy(&v, &w, 16);
+    return v;
+}
+
+template <int DT>
+__device__ __forceinline__ typename elem<DT>::T load_one(const void* base, int64_t j) {
+    return ((const typename elem<DT>::T*)base)[j];
+}
+
+// Store V consecutive elements of type OT (V * sizeof(OT) is a multiple of
+// 16 and the address is 16-byte aligned) with 16-byte stores.
+template <class OT, int V>
+__device__ __forceinline__ void store_run(void* base, int64_t j, const OT (&v)[V]) {
+    static_assert((V * sizeof(OT)) % 16 == 0, "store run must be whole vectors");
+    u32x4* p = (u32x4*)((char*)base + j * (int64_t)sizeof(OT));
+    const u32x4* src = (const u32x4*)v;
+#pragma unroll
+    for (int i = 0; i < (int)(V * sizeof(OT) / 16); ++i) __builtin_nontemporal_store(src[i], p + i);
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 primitives (DPP)
+// ---------------------------------------------------------------------------
+
+// DPP controls (GFX9 encoding).
+enum : int {
+    DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118,
+    DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143
+};
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x) {
+    // lanes whose source is out of the row, or whose row is masked off, get 0
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
+}
+
+template <int CTRL, int ROW_MASK, class T>
+__device__ __forceinline__ T dpp_move(T x) {
+    if constexpr (sizeof(T) == 4) {
+        uint32_t u = __builtin_bit_cast(uint32_t, x);
+        return __builtin_bit_cast(T, dpp32<CTRL, ROW_MASK>(u));
+    } else {
+        uint64_t u = __builtin_bit_cast(uint64_t, x);
+        uint32_t lo = dpp32<CTRL, ROW_MASK>((uint32_t)u);
+        uint32_t hi = dpp32<CTRL, ROW_MASK>((uint32_t)(u >> 32));
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Inclusive scan over the 64 lanes of a wave (lane order), identity 0.
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+    x = x + dpp_move<DPP_ROW_SHR1, 0xf>(x);
+    x = x + dpp_move<DPP_ROW_SHR2, 0xf>(x);
+    x = x + dpp_move<DPP_ROW_SHR4, 0xf>(x);
+    x = x + dpp_move<DPP_ROW_SHR8, 0xf>(x);
+    x = x + dpp_move<DPP_ROW_BCAST15, 0xa>(x);
+    x = x + dpp_move<DPP_ROW_BCAST31, 0xc>(x);
+    return x;
+}
+
+template <class T>
+__device__ __forceinline__ T readlane(T x, int lane) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
+    } else {
+        uint64_t u = __builtin_bit_cast(uint64_t, x);
+        uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+        uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Sum over the wave in a fixed tree order, result in every lane.
+template <class T>
+__device__ __forceinline__ T wave_sum(T x) {
+    return readlane(wave_incl_scan(x), 63);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// ---------------------------------------------------------------------------
+// Error-free transformations (binary32)
+// ---------------------------------------------------------------------------
+
+// Knuth's TwoSum: s + e == a + b exactly, s = fl(a + b).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    float bb = s - a;
+    float aa = s - bb;
+    e = (a - aa) + (b - bb);
+}
+
+// FMA-based TwoProduct: p + e == a * b exactly, p = fl(a * b).
+__device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
+    p = a * b;
+    e = __builtin_fmaf(a, b, -p);
+}
+
+// ---------------------------------------------------------------------------
+// Cross-workgroup status words
+// ---------------------------------------------------------------------------
+//
+// A 64-bit value published by one workgroup and read by others is stored as
+// two 64-bit words, each = (tag << 32) | 32 bits of the value. The tag is
+// the launch epoch, so words written by earlier launches never look valid
+// and the workspace needs no clearing between launches. Every access is an
+// agent-scope atomic, which keeps it coherent across the eight XCDs' L2s
+// without fences; a reader accepts the value only when both tags match.
+
+__device__ __forceinline__ uint64_t atomic_ld(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_st(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t atomic_ld32(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_st32(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t atomic_add32(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_or32(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void tagged_store(uint64_t* w, uint32_t tag, uint64_t v) {
+    atomic_st(w, ((uint64_t)tag << 32) | (uint32_t)v);
+    atomic_st(w + 1, ((uint64_t)tag << 32) | (uint32_t)(v >> 32));
+}
+
+// Returns true and the value when both halves carry `tag`.
+__device__ __forceinline__ bool tagged_load(const uint64_t* w, uint32_t tag, uint64_t& v) {
+    uint64_t a = atomic_ld(w);
+    uint64_t b = atomic_ld(w + 1);
+    v = (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)b << 32);
+    return (uint32_t)(a >> 32) == tag && (uint32_t)(b >> 32) == tag;
+}
+
+template <class T> __device__ __forceinline__ uint64_t to_bits(T v) {
+    if constexpr (sizeof(T) == 8) return __builtin_bit_cast(uint64_t, v);
+    else return (uint64_t)__builtin_bit_cast(uint32_t, v);
+}
+template <class T> __device__ __forceinline__ T from_bits(uint64_t b) {
+    if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, b);
+    else return __builtin_bit_cast(T, (uint32_t)b);
+}
+
+// Bounded spin: true while the deadline (wall clock, 100 MHz) is not past.
+__device__ __forceinline__ uint64_t now_ticks() { return wall_clock64(); }
+
+__device__ __forceinline__ Header* header(uint8_t* ws) { return (Header*)ws; }
+
+__device__ __forceinline__ uint32_t epoch_tag(uint32_t epoch) {
+    return (epoch % 0xFFFFFFFEu) + 1u;   // never 0 (fresh workspace) nor ~0
+}
+
+__device__ __forceinline__ void flag_error(uint8_t* ws, uint32_t bit) {
+    if (ws != nullptr) atomic_or32(&header(ws)->error, bit);
+}
+
+// Tag of the running launch: the prologue kernel that precedes every
+// launch using tags has already bumped the workspace epoch, so a plain load
+// (ordered after the prologue by the stream) gives every workgroup the same
+// value without any atomic.
+__device__ __forceinline__ uint32_t begin_launch(const uint8_t* ws) {
+    return epoch_tag(((const Header*)ws)->epoch);
+}
+
+// Arrival counter that needs no reset between launches: the word holds
+// (tag << 32) | count and a count under another tag reads as 0. Returns the
+// number of arrivals before this one in the current launch.
+__device__ __forceinline__ uint32_t tagged_count(uint64_t* c, uint32_t tag) {
+    uint64_t old = atomic_ld(c);
+    while (true) {
+        const uint32_t cnt = ((uint32_t)(old >> 32) == tag) ? (uint32_t)old : 0u;
+        const uint64_t nw = ((uint64_t)tag << 32) | (uint64_t)(cnt + 1u);
+        if (__hip_atomic_compare_exchange_strong(c, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return cnt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Segment / tile geometry
+// ---------------------------------------------------------------------------
+//
+// A segment of n elements whose first input starts `a` elements past a
+// 16-byte boundary is covered by tiles in a shifted index u = j + a: tile s
+// holds u in [s*TILE, (s+1)*TILE). Every tile but the first starts on a
+// 16-byte boundary of every pointer of the row, so interior vectors are
+// whole aligned 16-byte accesses. A row whose pointers are misaligned
+// relative to each other gets a = 0 and element-wise access (vec_ok = 0).
+// Tiles never straddle segments; the tiles of all segments are numbered
+// consecutively in segment order ("physical" tile index).
+
+struct SegInfo {
+    const void* in0;
+    const void* in1;
+    void* out0;
+    void* out1;
+    int64_t n;        // length
+    int64_t first;    // physical index of the segment's first tile
+    int64_t ntiles;
+    int64_t k;        // segment index
+    int32_t shift;    // a
+    int32_t vec_ok;
+};
+
+// Shift of a row: how many elements its first input starts past a 16-byte
+// boundary (0 when the pointer is not even element-aligned).
+__device__ __forceinline__ int32_t row_shift(const void* in0, int ies) {
+    const uintptr_t b0 = (uintptr_t)in0;
+    if (b0 % ies != 0) return 0;
+    return (int32_t)((b0 % 16) / ies);
+}
+
+// The fields of a table row that the kernels use, read one by one (ops
+// have arity <= 2 and at most 2 outputs).
+struct Row {
+    const void* in0;
+    const void* in1;
+    void* out0;
+    void* out1;
+    int64_t n;
+};
+
+__device__ __forceinline__ Row load_row(const dr_segment* rows, int64_t k) {
+    const dr_segment* p = rows + k;
+    Row r;
+    r.in0 = p->in[0];
+    r.in1 = p->in[1];
+    r.out0 = p->out[0];
+    r.out1 = p->out[1];
+    r.n = p->length;
+    return r;
+}
+
+__device__ __forceinline__ bool aligned_at(const void* p, uintptr_t j0, int es) {
+    return (((uintptr_t)p + j0 * (uintptr_t)es) % 16) == 0;
+}
+
+// Whether every pointer of the row is 16-byte aligned at the first index
+// where the first input is (so whole 16-byte vectors can be used).
+__device__ __forceinline__ int32_t row_vec_ok(const Row& r, int32_t shift, int arity, int nout, int ies,
+                                              int oes) {
+    const int V = 16 / ies;
+    const uintptr_t j0 = (uintptr_t)((V - shift) % V);
+    bool ok = aligned_at(r.in0, j0, ies);
+    if (arity > 1) ok = ok && aligned_at(r.in1, j0, ies);
+    if (nout > 0) ok = ok && aligned_at(r.out0, j0, oes);
+    if (nout > 1) ok = ok && aligned_at(r.out1, j0, oes);
+    return ok ? 1 : 0;
+}
+
+__device__ __forceinline__ int64_t tiles_of(int64_t n, int32_t shift, int64_t tile) {
+    return n > 0 ? (n + shift + tile - 1) / tile : 0;
+}
+
+__device__ __forceinline__ bool row_bad(const Row& r, int arity, int nout) {
+    if (r.n < 0) return true;
+    if (r.n == 0) return false;
+    if (r.in0 == nullptr) return true;
+    if (arity > 1 && r.in1 == nullptr) return true;
+    if (nout > 0 && r.out0 == nullptr) return true;
+    if (nout > 1 && r.out1 == nullptr) return true;
+    return false;
+}
+
+// The tiles of the launch as seen by one wave (every lane must call the
+// methods). Small tables (m <= DR_SMALL_TABLE) are planned here, one row
+// per lane; large ones read the plan dr_plan left in the workspace, whose
+// key (rows, m, total, tile, input element size) must match the launch.
+struct TileMap {
+    int64_t total_tiles = 0;
+    bool ok = false;
+    // small-table state, one row per lane
+    int64_t cnt = 0, incl = 0, n = 0;
+    int32_t shift = 0, vec_ok = 0;
+    uint32_t plan_tag = 0;   // large tables: tag of the plan words
+
+    __device__ __forceinline__ void init(const LaunchArgs& a) {
+        const int lane = lane_id();
+        if (a.m <= DR_SMALL_TABLE) {
+            bool bad = false;
+            if (lane < a.m) {
+                const Row r = load_row(a.rows, lane);
+                bad = row_bad(r, a.arity, a.nout);
+                if (!bad) {
+                    n = r.n;
+                    shift = row_shift(r.in0, a.ies);
+                    vec_ok = row_vec_ok(r, shift, a.arity, a.nout, a.ies, a.oes);
+                }
+            }
+            cnt = tiles_of(n, shift, a.tile);
+            incl = wave_incl_scan(cnt);
+            const int64_t nsum = wave_sum(n);
+            const bool anybad = __ballot(bad) != 0;
+            total_tiles = readlane(incl, 63);
+            ok = !anybad && nsum == a.total && total_tiles <= a.tmax;
+            if (!ok) {
+                if (threadIdx.x == 0)
+                    flag_error(a.ws, (anybad || nsum != a.total) ? DR_DEVFLAG_BAD_TABLE
+                                                                 : DR_DEVFLAG_TOO_MANY_TILES);
+                total_tiles = 0;
+            }
+            return;
+        }
+        const Header* h = (const Header*)a.ws;
+        ok = a.ws != nullptr && h->plan_m == a.m && h->plan_rows == (uint64_t)(uintptr_t)a.rows &&
+             h->plan_tile == a.tile && h->plan_ies == a.ies && h->plan_total == a.total;
+        plan_tag = ok ? h->plan_tag : 0u;
+        if (!ok) {
+            if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_PLAN);
+            return;
+        }
+        total_tiles = h->plan_tiles;
+        if (total_tiles > a.tmax) {
+            if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_TOO_MANY_TILES);
+            total_tiles = 0;
+            ok = false;
+        }
+    }
+
+    // Segment owning physical tile t (0 <= t < total_tiles). Returns false
+    // (and flags the fault) when the row lacks a pointer the launch needs.
+    __device__ __forceinline__ bool find(const LaunchArgs& a, int64_t t, SegInfo& si) const {
+        int k;
+        if (a.m <= DR_SMALL_TABLE) {
+            const uint64_t le = __ballot(lane_id() < a.m && incl <= t);
+            k = __builtin_popcountll(le);   // segments ending at or before tile t
+            si.first = readlane(incl - cnt, k);
+            si.ntiles = readlane(cnt, k);
+            si.n = readlane(n, k);
+            si.shift = readlane(shift, k);
+            si.vec_ok = readlane(vec_ok, k);
+        } else {
+            const uint64_t* F = (const uint64_t*)(a.ws + a.lay.off_plan_first);
+            const uint64_t* tseg = (const uint64_t*)(a.ws + a.lay.off_plan_tseg);
+            const uint64_t wk = tseg[t];
+            const uint32_t kk = (uint32_t)wk;
+            const bool kok = (uint32_t)(wk >> 32) == plan_tag && (int64_t)kk < a.m;
+            const uint64_t f0 = kok ? F[kk] : 0, f1 = kok ? F[kk + 1] : 0;
+            if (!kok || (uint32_t)(f0 >> 32) != plan_tag || (uint32_t)(f1 >> 32) != plan_tag) {
+                if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_PLAN);
+                return false;
+            }
+            k = (int)kk;
+            si.first = (uint32_t)f0;
+            si.ntiles = (int64_t)(uint32_t)f1 - (int64_t)(uint32_t)f0;
+            const Row r = load_row(a.rows, k);
+            if (row_bad(r, a.arity, a.nout)) {
+                if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_BAD_TABLE);
+                return false;
+            }
+            si.n = r.n;
+            si.shift = row_shift(r.in0, a.ies);
+            si.vec_ok = row_vec_ok(r, si.shift, a.arity, a.nout, a.ies, a.oes);
+        }
+        si.k = k;
+        const Row r = load_row(a.rows, k);
+        si.in0 = r.in0;
+        si.in1 = r.in1;
+        si.out0 = r.out0;
+        si.out1 = r.out1;
+        return true;
+    }
+};
+
+// Bounded wait helper.
+struct Deadline {
+    uint64_t end;
+    __device__ __forceinline__ explicit Deadline(uint64_t ticks) : end(now_ticks() + ticks) {}
+    __device__ __forceinline__ bool passed() const { return now_ticks() > end; }
+};
+
+// ---------------------------------------------------------------------------
+// Tile access
+// ---------------------------------------------------------------------------
+//
+// A tile of TILE = 256 * ITEMS elements is SLOTS = ITEMS / V vectors per
+// thread. Wave w owns the contiguous run of vectors [w*SLOTS*64,
+// (w+1)*SLOTS*64) of the tile, and slot s of lane l is vector
+// (w*SLOTS + s)*64 + l: each load instruction of a wave covers 1 KiB of
+// consecutive memory. In reverse mode the vector order of the tile is
+// mirrored (vector p in processing order is vector NV-1-p in memory).
+
+template <int DT> __device__ __forceinline__ typename elem<DT>::T zero_elem() {
+    return (typename elem<DT>::T)0;
+}
+
+template <int DT, int SLOTS>
+__device__ __forceinline__ void load_slots(vec<DT> (&x)[SLOTS], const void* base, const SegInfo& si,
+                                           int64_t u0, int w, int l, bool rev) {
+    constexpr int V = vwidth<DT>();
+    constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int64_t p = (int64_t)(w * SLOTS + s) * 64 + l;
+        const int64_t q = rev ? (NV - 1 - p) : p;
+        const int64_t j = u0 + q * V - si.shift;
+        if (si.vec_ok && j >= 0 && j + V <= si.n) {
+            x[s] = load_vec<DT>(base, j);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t jj = j + e;
+                typename elem<DT>::T v = zero_elem<DT>();
+                if (jj >= 0 && jj < si.n) v = load_one<DT>(base, jj);
+                x[s].e[e] = v;
+            }
+        }
+    }
+}
+
+// Store the V outputs of slot s (given in memory order).
+template <class OT, int V, int SLOTS>
+__device__ __forceinline__ void store_slot(void* base, const SegInfo& si, int64_t u0, int w, int l,
+                                           int s, bool rev, const OT (&o)[V]) {
+    constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+    const int64_t p = (int64_t)(w * SLOTS + s) * 64 + l;
+    const int64_t q = rev ? (NV - 1 - p) : p;
+    const int64_t j = u0 + q * V - si.shift;
+    if (si.vec_ok && j >= 0 && j + V <= si.n) {
+        store_run<OT, V>(base, j, o);
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int64_t jj = j + e;
+            if (jj >= 0 && jj < si.n) ((OT*)base)[jj] = o[e];
+        }
+    }
+}
+
+// Mirror the element order of a small register array when `rev` (static
+// indices, so the compiler emits selects rather than indexed registers).
+template <class T, int V>
+__device__ __forceinline__ void mirror_if(T (&v)[V], bool rev) {
+#pragma unroll
+    for (int e = 0; e < V / 2; ++e) {
+        T a = v[e], b = v[V - 1 - e];
+        v[e] = rev ? b : a;
+        v[V - 1 - e] = rev ? a : b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// View transforms
+// ---------------------------------------------------------------------------
+
+// Value of the view in the accumulation type of a reduction/scan (the
+// product of two binary32 values is formed in binary32 here; the
+// compensated reduction recovers its rounding error separately).
+template <int OP, class A>
+__device__ __forceinline__ A view_apply(A x0, A x1, A alpha) {
+    if constexpr (OP == DR_OP_IDENTITY) return x0;
+    else if constexpr (OP == DR_OP_SQUARE) return x0 * x0;
+    else if constexpr (OP == DR_OP_MUL) return x0 * x1;
+    else return x0 + alpha * x1;
+}
+
+}  // namespace dr

@@ -1,0 +1,100 @@
+// dr_internal.hpp — layout of the caller's workspace and the launcher
+// registry shared by the host API (dr_api.cpp) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dr.h"
+
+namespace dr {
+
+// Device fault flags (dr_device_status).
+enum : uint32_t {
+    DR_DEVFLAG_BAD_TABLE = 1u,
+    DR_DEVFLAG_TIMEOUT = 2u,
+    DR_DEVFLAG_PLAN = 4u,
+    DR_DEVFLAG_TOO_MANY_TILES = 8u
+};
+
+constexpr int kBlock = 256;            // threads per workgroup (4 waves)
+constexpr int kGroupTiles = 64;        // tiles per first-level combine group
+
+// First 256 bytes of every workspace.
+struct Header {
+    uint32_t error;      // DR_DEVFLAG_* bits, sticky until dr_device_status
+    uint32_t epoch;      // launches on this workspace; bumped by each launch's prologue
+    uint32_t plan_tag;   // tag of the launch that wrote the plan words
+    uint32_t pad0;
+    uint64_t plan_rows;  // key of the plan built by dr_plan
+    int64_t plan_m;
+    int64_t plan_tile;
+    int64_t plan_total;
+    int64_t plan_tiles;  // tile count of the planned table
+    int32_t plan_ies;
+    int32_t plan_arity;
+    uint8_t pad[256 - 4 * 4 - 8 * 5 - 4 * 2];
+};
+static_assert(sizeof(Header) == 256, "header is 256 bytes");
+
+// Fixed part of every workspace: the header. Variable sections follow.
+constexpr uint64_t kFixedBytes = sizeof(Header);
+
+// Byte offsets of the variable workspace sections (all 256-byte aligned).
+// Every 64-bit word in them is tagged with the epoch of the launch (or
+// plan) that wrote it, so stale contents of any layout are never mistaken
+// for current ones.
+struct WsLayout {
+    uint64_t off_plan_first;   // tagged [m + 1]: first tile of each segment (large tables)
+    uint64_t off_plan_tseg;    // tagged [tmax]: segment of each tile (large tables)
+    uint64_t off_tile;         // [tmax * tile_words]: per-tile (or per-workgroup) tagged words
+    uint64_t off_gcnt;         // tagged counters [ngroups]: arrivals per combine group
+    uint64_t off_gpart;        // [ngroups * 2]: tagged group partials
+    uint64_t off_ucnt;         // tagged counters [nunits]: arrived groups per result
+    uint64_t bytes;            // total size
+    int32_t tile_words;        // 64-bit words per tile
+    int32_t part_word;         // first word of the reduce partial inside a tile's words
+};
+
+// Launch-wide arguments shared by the kernels (passed by value).
+struct LaunchArgs {
+    const dr_segment* rows;
+    int64_t m;
+    int64_t total;
+    int64_t tile;         // elements per tile
+    int64_t tmax;         // grid size = bound on the tile count
+    int32_t ies;          // input element size
+    int32_t oes;          // output element size (0: no output)
+    int32_t mode;
+    uint32_t flags;
+    int32_t arity;
+    int32_t nout;
+    double alpha;
+    uint8_t* ws;
+    WsLayout lay;
+    void* result;
+    double init_f;
+    int64_t init_i;
+    const double* g;
+    uint64_t spin_ticks;  // bound of every wait, wall-clock ticks
+};
+
+// Launches the kernel with `grid` workgroups, one per tile (kernels that use
+// tags are preceded by the epoch prologue).
+typedef hipError_t (*LaunchFn)(const LaunchArgs& a, int64_t grid, hipStream_t stream);
+
+// The one-thread prologue of every launch that uses tags: epoch + 1.
+hipError_t launch_epoch_bump(uint8_t* ws, hipStream_t stream);
+
+// Kernel lookup. `items` is the elements per thread of the tile. Each
+// returns nullptr when the combination is not built.
+LaunchFn find_for_each(int in_dt, int out_dt, int op, int items);
+LaunchFn find_reduce(int in_dt, int op, int acc, int items);
+LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items);
+LaunchFn find_scan_reduce(int in_dt, int reduce_op, int acc, int items);
+LaunchFn find_broadcast_mul(int in_dt, int op, int items);
+hipError_t launch_plan(const LaunchArgs& a, hipStream_t stream);     // prefix + tile -> segment map
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);  // fill with 0 (graph safe)
+
+
+}  // namespace dr

@@ -1,0 +1,211 @@
+// k_elementwise.hip — for_each over a zip/transform view (section 4.3,
+// "for_each"; the stream triad of section 5.1) and the adjoint of
+// transform_reduce (a broadcast multiply by the upstream gradient).
+//
+// One workgroup per tile; a tile lies inside one segment. Both kernels are
+// pure streams over HBM: each input byte is read once with 16-byte
+// non-temporal loads and each output byte written once.
+#include "dr_device.hpp"
+
+namespace dr {
+
+// The view element in the output type, one rounding per operation (the
+// library is built with -ffp-contract=off, so a + s*b is not fused).
+template <int IDT, int ODT, int OP>
+struct EwOp;
+
+template <int IDT, int OP>
+struct EwOp<IDT, DR_F32, OP> {   // F32 / BF16 inputs -> F32
+    using O = float;
+    __device__ __forceinline__ static O apply(typename elem<IDT>::T x, typename elem<IDT>::T y,
+                                              float alpha) {
+        float x0 = decode<IDT>(x);
+        if constexpr (OP == DR_OP_IDENTITY) return x0;
+        else if constexpr (OP == DR_OP_SQUARE) return x0 * x0;
+        else if constexpr (OP == DR_OP_MUL) return x0 * decode<IDT>(y);
+        else {
+            float t = alpha * decode<IDT>(y);
+            return x0 + t;
+        }
+    }
+};
+
+template <int OP>
+struct EwOp<DR_F64, DR_F64, OP> {
+    using O = double;
+    __device__ __forceinline__ static O apply(double x, double y, double alpha) {
+        if constexpr (OP == DR_OP_IDENTITY) return x;
+        else if constexpr (OP == DR_OP_SQUARE) return x * x;
+        else if constexpr (OP == DR_OP_MUL) return x * y;
+        else {
+            double t = alpha * y;
+            return x + t;
+        }
+    }
+};
+
+template <int OP>
+struct EwOp<DR_I32, DR_I32, OP> {   // two's complement wrap
+    using O = int32_t;
+    __device__ __forceinline__ static O apply(int32_t x, int32_t y, int64_t alpha) {
+        uint32_t a = (uint32_t)x, b = (uint32_t)y;
+        if constexpr (OP == DR_OP_IDENTITY) return x;
+        else if constexpr (OP == DR_OP_SQUARE) return (int32_t)(a * a);
+        else if constexpr (OP == DR_OP_MUL) return (int32_t)(a * b);
+        else return (int32_t)(a + (uint32_t)(uint64_t)alpha * b);
+    }
+};
+
+template <int OP>
+struct EwOp<DR_I32, DR_I64, OP> {   // exact
+    using O = int64_t;
+    __device__ __forceinline__ static O apply(int32_t x, int32_t y, int64_t alpha) {
+        int64_t a = x, b = y;
+        if constexpr (OP == DR_OP_IDENTITY) return a;
+        else if constexpr (OP == DR_OP_SQUARE) return a * a;
+        else if constexpr (OP == DR_OP_MUL) return a * b;
+        else return a + alpha * b;
+    }
+};
+
+template <int IDT, int ODT>
+__device__ __forceinline__ auto alpha_of(double alpha) {
+    if constexpr (ODT == DR_F32) return (float)alpha;
+    else if constexpr (ODT == DR_F64) return alpha;
+    else return (int64_t)alpha;
+}
+
+template <int IDT, int ODT, int OP, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_for_each(LaunchArgs a) {
+    constexpr int V = vwidth<IDT>();
+    constexpr int SLOTS = ITEMS / V;
+    constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
+    using Op = EwOp<IDT, ODT, OP>;
+    using O = typename Op::O;
+
+    TileMap tm;
+    tm.init(a);
+    const int64_t t = blockIdx.x;
+    if (!tm.ok || t >= tm.total_tiles) return;
+    SegInfo si;
+    if (!tm.find(a, t, si)) return;
+    const int w = threadIdx.x >> 6, l = lane_id();
+    const int64_t u0 = (t - si.first) * a.tile;
+    const auto alpha = alpha_of<IDT, ODT>(a.alpha);
+
+    vec<IDT> x[SLOTS], y[SLOTS];
+    load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, false);
+    if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, false);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        O o[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            typename elem<IDT>::T yv = ZIP ? y[s].e[e] : zero_elem<IDT>();
+            o[e] = Op::apply(x[s].e[e], yv, alpha);
+        }
+        store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, false, o);
+    }
+}
+
+// d op / d x_which, evaluated in binary64 (exact for F32/BF16 inputs).
+template <int IDT, int OP>
+__device__ __forceinline__ double dview(typename elem<IDT>::T x, typename elem<IDT>::T y, int which,
+                                        double alpha) {
+    if constexpr (OP == DR_OP_IDENTITY) return 1.0;
+    else if constexpr (OP == DR_OP_SQUARE) return 2.0 * (double)decode<IDT>(x);
+    else if constexpr (OP == DR_OP_MUL) return which == 0 ? (double)decode<IDT>(y) : (double)decode<IDT>(x);
+    else return which == 0 ? 1.0 : alpha;
+}
+
+template <int IDT, int OP, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_broadcast_mul(LaunchArgs a) {
+    constexpr int V = vwidth<IDT>();
+    constexpr int SLOTS = ITEMS / V;
+    constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
+    using O = typename std::conditional<IDT == DR_F64, double, float>::type;
+
+    TileMap tm;
+    tm.init(a);
+    const int64_t t = blockIdx.x;
+    if (!tm.ok || t >= tm.total_tiles) return;
+    SegInfo si;
+    if (!tm.find(a, t, si)) return;
+    const int w = threadIdx.x >> 6, l = lane_id();
+    const int64_t u0 = (t - si.first) * a.tile;
+    const double g = a.g[a.mode == DR_MODE_BATCH ? si.k : 0];
+
+    vec<IDT> x[SLOTS], y[SLOTS];
+    if constexpr (OP != DR_OP_IDENTITY) load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, false);
+    if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, false);
+    for (int which = 0; which < a.nout; ++which) {
+        void* out = which == 0 ? si.out0 : si.out1;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            O o[V];
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                typename elem<IDT>::T xv = OP != DR_OP_IDENTITY ? x[s].e[e] : zero_elem<IDT>();
+                typename elem<IDT>::T yv = ZIP ? y[s].e[e] : zero_elem<IDT>();
+                o[e] = (O)(g * dview<IDT, OP>(xv, yv, which, a.alpha));
+            }
+            store_slot<O, V, SLOTS>(out, si, u0, w, l, s, false, o);
+        }
+    }
+}
+
+template <int IDT, int ODT, int OP, int ITEMS>
+hipError_t launch_for_each(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
+    hipLaunchKernelGGL((k_for_each<IDT, ODT, OP, ITEMS>), dim3((uint32_t)grid), dim3(kBlock), 0,
+                       stream, a);
+    return hipGetLastError();
+}
+
+template <int IDT, int OP, int ITEMS>
+hipError_t launch_broadcast_mul(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
+    hipLaunchKernelGGL((k_broadcast_mul<IDT, OP, ITEMS>), dim3((uint32_t)grid), dim3(kBlock), 0,
+                       stream, a);
+    return hipGetLastError();
+}
+
+#define DR_EW_OPS(IDT, ODT, ITEMS)                                                   \
+    if (in_dt == IDT && out_dt == ODT && items == ITEMS) {                           \
+        switch (op) {                                                                \
+        case DR_OP_IDENTITY: return launch_for_each<IDT, ODT, DR_OP_IDENTITY, ITEMS>; \
+        case DR_OP_SQUARE: return launch_for_each<IDT, ODT, DR_OP_SQUARE, ITEMS>;     \
+        case DR_OP_MUL: return launch_for_each<IDT, ODT, DR_OP_MUL, ITEMS>;           \
+        case DR_OP_AXPY: return launch_for_each<IDT, ODT, DR_OP_AXPY, ITEMS>;         \
+        default: return nullptr;                                                     \
+        }                                                                            \
+    }
+
+LaunchFn find_for_each(int in_dt, int out_dt, int op, int items) {
+    DR_EW_OPS(DR_F32, DR_F32, 16)
+    DR_EW_OPS(DR_F32, DR_F32, 32)
+    DR_EW_OPS(DR_BF16, DR_F32, 16)
+    DR_EW_OPS(DR_BF16, DR_F32, 32)
+    DR_EW_OPS(DR_F64, DR_F64, 16)
+    DR_EW_OPS(DR_I32, DR_I32, 16)
+    DR_EW_OPS(DR_I32, DR_I64, 16)
+    return nullptr;
+}
+
+#define DR_BM_OPS(IDT, ITEMS)                                                   \
+    if (in_dt == IDT && items == ITEMS) {                                       \
+        switch (op) {                                                           \
+        case DR_OP_IDENTITY: return launch_broadcast_mul<IDT, DR_OP_IDENTITY, ITEMS>; \
+        case DR_OP_SQUARE: return launch_broadcast_mul<IDT, DR_OP_SQUARE, ITEMS>;     \
+        case DR_OP_MUL: return launch_broadcast_mul<IDT, DR_OP_MUL, ITEMS>;           \
+        case DR_OP_AXPY: return launch_broadcast_mul<IDT, DR_OP_AXPY, ITEMS>;         \
+        default: return nullptr;                                                \
+        }                                                                       \
+    }
+
+LaunchFn find_broadcast_mul(int in_dt, int op, int items) {
+    DR_BM_OPS(DR_F32, 16)
+    DR_BM_OPS(DR_BF16, 16)
+    DR_BM_OPS(DR_F64, 16)
+    return nullptr;
+}
+
+}  // namespace dr

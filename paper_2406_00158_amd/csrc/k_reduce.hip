@@ -1,0 +1,185 @@
+// k_reduce.hip — transform_reduce over a zip/transform view of a segmented
+// range (section 4.3, "reduce"; Algorithm 1 is the dot product
+// zip | transform(l*r) | reduce, Algorithm 3 the per-segment partials that
+// are combined afterwards).
+//
+// One workgroup per tile (a tile lies inside one segment). Each thread
+// accumulates its ITEMS elements, the workgroup reduces them to one tile
+// partial, and the partials are combined deterministically in the same
+// launch (dr_combine.hpp): over the whole range in CONCAT mode, per segment
+// in BATCH mode. No second pass, no host-side combine, and no atomic that
+// every workgroup hits (a one-thread prologue bumps the launch epoch).
+//
+// Accumulation inside a tile:
+//  - int32 inputs: int64, exact.
+//  - binary32 / bfloat16 inputs, PLAIN: binary32 running sums and a
+//    binary32 tree; the tile partial is widened to binary64.
+//  - COMPENSATED: a binary32 (sum, error) pair per thread: TwoSum (Knuth) on
+//    every addition and an FMA-based TwoProduct for products, which keeps
+//    each rounding error of the binary32 arithmetic. The pair is widened to
+//    binary64 (exactly) at the end of the tile and the tree runs in binary64.
+//  - binary64 inputs: binary64 sums.
+// Partials are combined across tiles and segments in binary64 (or int64).
+#include "dr_combine.hpp"
+
+namespace dr {
+
+template <int IDT>
+using partial_t = typename std::conditional<IDT == DR_I32, int64_t, double>::type;
+
+// Sum of the view over one tile, returned in thread 0 (whole workgroup).
+template <int IDT, int OP, int ACC, int ITEMS>
+__device__ __forceinline__ partial_t<IDT> tile_partial(const LaunchArgs& a, const SegInfo& si, int64_t t) {
+    constexpr int V = vwidth<IDT>();
+    constexpr int SLOTS = ITEMS / V;
+    constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
+    constexpr int WAVES = kBlock / 64;
+    using P = partial_t<IDT>;
+    constexpr bool F32PATH = (IDT == DR_F32 || IDT == DR_BF16);
+    __shared__ P s_wave[WAVES];
+    __shared__ float s_wavef[WAVES];
+
+    const int w = threadIdx.x >> 6, l = lane_id();
+    const int64_t u0 = (t - si.first) * a.tile;
+    vec<IDT> x[SLOTS], y[SLOTS];
+    load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, false);
+    if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, false);
+
+    P part = (P)0;
+    if constexpr (F32PATH && ACC == DR_ACC_COMPENSATED) {
+        const float alpha = (float)a.alpha;
+        float s = 0.0f, c = 0.0f;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const float x0 = decode<IDT>(x[q].e[e]);
+                float p, pe;
+                if constexpr (OP == DR_OP_IDENTITY) {
+                    p = x0;
+                    pe = 0.0f;
+                } else if constexpr (OP == DR_OP_SQUARE) {
+                    two_prod(x0, x0, p, pe);
+                } else if constexpr (OP == DR_OP_MUL) {
+                    two_prod(x0, decode<IDT>(y[q].e[e]), p, pe);
+                } else {
+                    float m, me, r;
+                    two_prod(alpha, decode<IDT>(y[q].e[e]), m, me);
+                    two_sum(x0, m, p, r);
+                    pe = r + me;
+                }
+                float err;
+                two_sum(s, p, s, err);
+                c += err + pe;
+            }
+        }
+        P tp = (double)s + (double)c;   // exact unless s is not finite
+        if (!__builtin_isfinite(s)) tp = (double)s;
+        const P wsum = wave_sum(tp);
+        if (l == 0) s_wave[w] = wsum;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int i = 0; i < WAVES; ++i) part += s_wave[i];
+    } else if constexpr (F32PATH) {
+        const float alpha = (float)a.alpha;
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const float x0 = decode<IDT>(x[q].e[e]);
+                const float x1 = ZIP ? decode<IDT>(y[q].e[e]) : 0.0f;
+                acc += view_apply<OP, float>(x0, x1, alpha);
+            }
+        }
+        const float wsum = wave_sum(acc);
+        if (l == 0) s_wavef[w] = wsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float pf = 0.0f;
+            for (int i = 0; i < WAVES; ++i) pf += s_wavef[i];
+            part = (double)pf;
+        }
+    } else {
+        // int32 -> int64 exact, or binary64
+        using A = P;
+        const A alpha = (A)a.alpha;
+        A acc = (A)0;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const A x0 = (A)decode<IDT>(x[q].e[e]);
+                const A x1 = ZIP ? (A)decode<IDT>(y[q].e[e]) : (A)0;
+                acc += view_apply<OP, A>(x0, x1, alpha);
+            }
+        }
+        const A wsum = wave_sum(acc);
+        if (l == 0) s_wave[w] = wsum;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int i = 0; i < WAVES; ++i) part += s_wave[i];
+    }
+    __syncthreads();   // s_wave is reused by the next tile
+    return part;
+}
+
+// One workgroup per tile (tile = block index).
+template <int IDT, int OP, int ACC, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_reduce(LaunchArgs a) {
+    using P = partial_t<IDT>;
+    const uint32_t tag = begin_launch(a.ws);
+    TileMap tm;
+    tm.init(a);
+    if (!tm.ok) return;
+    const int64_t T = tm.total_tiles;
+    const int64_t t = blockIdx.x;
+    if (t < T) {
+        SegInfo si;
+        if (!tm.find(a, t, si)) return;
+        const P part = tile_partial<IDT, OP, ACC, ITEMS>(a, si, t);
+        if (a.mode == DR_MODE_BATCH) combine_tile_batch<P>(a, tag, t, si, part);
+        else combine_member<P>(a, tag, 0, 0, t, T, 0, part);
+    } else if (t == 0 && threadIdx.x == 0) {   // no tiles at all
+        if (a.mode == DR_MODE_BATCH) write_all_init<P>(a);
+        else write_result<P>(a, 0, (P)0);
+    }
+}
+
+template <int IDT, int OP, int ACC, int ITEMS>
+hipError_t launch_reduce(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
+    hipError_t e = launch_epoch_bump(a.ws, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_reduce<IDT, OP, ACC, ITEMS>), dim3((uint32_t)grid), dim3(kBlock), 0,
+                       stream, a);
+    return hipGetLastError();
+}
+
+#define DR_RED_OPS(IDT, ACC, ITEMS)                                                   \
+    if (in_dt == IDT && acc == ACC && items == ITEMS) {                               \
+        switch (op) {                                                                 \
+        case DR_OP_IDENTITY: return launch_reduce<IDT, DR_OP_IDENTITY, ACC, ITEMS>;   \
+        case DR_OP_SQUARE: return launch_reduce<IDT, DR_OP_SQUARE, ACC, ITEMS>;       \
+        case DR_OP_MUL: return launch_reduce<IDT, DR_OP_MUL, ACC, ITEMS>;             \
+        case DR_OP_AXPY: return launch_reduce<IDT, DR_OP_AXPY, ACC, ITEMS>;           \
+        default: return nullptr;                                                      \
+        }                                                                             \
+    }
+
+LaunchFn find_reduce(int in_dt, int op, int acc, int items) {
+    // integer and binary64 reductions ignore `acc`
+    if (in_dt == DR_I32 || in_dt == DR_F64) acc = DR_ACC_PLAIN;
+    DR_RED_OPS(DR_F32, DR_ACC_COMPENSATED, 16)
+    DR_RED_OPS(DR_F32, DR_ACC_COMPENSATED, 32)
+    DR_RED_OPS(DR_F32, DR_ACC_PLAIN, 16)
+    DR_RED_OPS(DR_F32, DR_ACC_PLAIN, 32)
+    DR_RED_OPS(DR_BF16, DR_ACC_COMPENSATED, 16)
+    DR_RED_OPS(DR_BF16, DR_ACC_COMPENSATED, 32)
+    DR_RED_OPS(DR_BF16, DR_ACC_PLAIN, 16)
+    DR_RED_OPS(DR_BF16, DR_ACC_PLAIN, 32)
+    DR_RED_OPS(DR_I32, DR_ACC_PLAIN, 16)
+    DR_RED_OPS(DR_F64, DR_ACC_PLAIN, 16)
+    return nullptr;
+}
+
+}  // namespace dr

@@ -1,0 +1,180 @@
+"""The C ABI library loads, exports every entry point include/dr.h declares,
+and rejects malformed arguments on the host before touching the GPU.
+CPU only: every call here fails its host checks, so no kernel is launched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2406_00158_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dr.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(B.LIB_PATH), reason="libdr.so not built")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dr_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = B.lib()
+    names = _declared()
+    assert "dr_for_each" in names and "dr_inclusive_scan" in names and "dr_transform_reduce" in names
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in dr.h but not exported"
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_version_and_status_strings():
+    L = B.lib()
+    assert L.dr_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.dr_status_string(code).decode()
+    assert L.dr_status_string(12345).decode() == "unknown status"
+
+
+def _host_table(rows, total, mode=B.DR_MODE_CONCAT):
+    arr = (B.dr_segment * max(1, len(rows)))()
+    for k, (ins, outs, n) in enumerate(rows):
+        for i, p in enumerate(ins):
+            arr[k].in_[i] = p
+        for i, p in enumerate(outs):
+            arr[k].out[i] = p
+        arr[k].length = n
+    # `rows` (device) gets a non-NULL dummy: the host checks fail before any use
+    t = B.dr_table(0x1000, ctypes.addressof(arr), len(rows), total, mode, 0)
+    return t, arr
+
+
+A, Bp, O = 0x10000000, 0x20000000, 0x30000000
+
+
+def _call_scan(t, view, out_dtype=B.DR_F32, flags=0, ws=0x40000000, ws_bytes=1 << 30):
+    return B.lib().dr_inclusive_scan(ctypes.byref(t), ctypes.byref(view), out_dtype, flags, ws, ws_bytes,
+                                     None, None)
+
+
+def test_view_and_table_errors():
+    L = B.lib()
+    t, keep = _host_table([((A,), (O,), 10)], 10)
+    bad_arity = B.dr_view(2, B.DR_F32, B.DR_OP_IDENTITY, 0, 0.0)
+    assert _call_scan(t, bad_arity) == -1
+    assert b"arity" in L.dr_last_error()
+    bad_op = B.dr_view(1, B.DR_F32, 99, 0, 0.0)
+    assert _call_scan(t, bad_op) == -1
+    bad_dtype = B.dr_view(1, 77, B.DR_OP_IDENTITY, 0, 0.0)
+    assert _call_scan(t, bad_dtype) == -2
+    v = B.make_view("identity", B.DR_F32)
+    assert _call_scan(t, v, out_dtype=B.DR_I64) == -2        # f32 -> i64 not a scan pair
+    assert _call_scan(t, v, flags=0x80) == -1                # unknown flag
+    vi = B.make_view("identity", B.DR_I32)
+    assert _call_scan(t, vi, out_dtype=B.DR_I64, flags=B.DR_SCAN_CARRY_F32) == -1
+    assert L.dr_inclusive_scan(None, ctypes.byref(v), B.DR_F32, 0, 0, 0, None, None) == -1
+    t2 = B.dr_table(0x1000, None, 1, 10, 7, 0)               # unknown mode
+    assert _call_scan(t2, v) == -1
+    t3 = B.dr_table(0x1000, None, -1, 10, 0, 0)
+    assert _call_scan(t3, v) == -1
+    vi_axpy = B.dr_view(2, B.DR_I32, B.DR_OP_AXPY, 0, 0.5)   # int axpy needs integer alpha
+    assert _call_scan(t, vi_axpy, out_dtype=B.DR_I64) == -1
+    del keep
+
+
+def test_host_row_errors():
+    v = B.make_view("identity", B.DR_F32)
+    t, keep = _host_table([((A,), (O,), -1)], -1 + 0)
+    assert _call_scan(t, v) == -1                             # negative total_length
+    t, keep = _host_table([((A,), (O,), -5), ((A,), (O,), 10)], 5)
+    assert _call_scan(t, v) == -1 and b"negative length" in B.lib().dr_last_error()
+    t, keep = _host_table([((A,), (O,), 10), ((A + 40,), (O + 40,), 10)], 21)
+    assert _call_scan(t, v) == -1 and b"sum of lengths" in B.lib().dr_last_error()
+    t, keep = _host_table([((0,), (O,), 10)], 10)
+    assert _call_scan(t, v) == -1 and b"NULL" in B.lib().dr_last_error()
+    t, keep = _host_table([((A,), (0,), 10)], 10)
+    assert _call_scan(t, v) == -1 and b"NULL" in B.lib().dr_last_error()
+    t, keep = _host_table([((A + 2,), (O,), 10)], 10)         # float pointer not 4-byte aligned
+    assert _call_scan(t, v) == -1 and b"aligned" in B.lib().dr_last_error()
+    # output overlapping another row's input
+    t, keep = _host_table([((A,), (O,), 10), ((O + 8,), (O + 400,), 10)], 20)
+    assert _call_scan(t, v) == -1 and b"overlaps" in B.lib().dr_last_error()
+    # two outputs overlapping
+    t, keep = _host_table([((A,), (O,), 10), ((A + 40,), (O + 20,), 10)], 20)
+    assert _call_scan(t, v) == -1 and b"overlaps" in B.lib().dr_last_error()
+    # in-place of a non-identity view is rejected; in-place identity scan passes
+    # the host checks (it then needs a GPU, so only the failing case is run)
+    sq = B.make_view("square", B.DR_F32)
+    t, keep = _host_table([((A,), (A,), 10)], 10)
+    assert _call_scan(t, sq) == -1
+    del keep
+
+
+def test_workspace_errors_and_sizes():
+    L = B.lib()
+    v = B.make_view("mul", B.DR_F32)
+    size = ctypes.c_size_t(0)
+    assert L.dr_workspace_bytes(B.DR_ALGO_REDUCE, 8, 1 << 28, ctypes.byref(v), None, ctypes.byref(size)) == 0
+    small = size.value
+    assert small >= 256 and small % 256 == 0
+    assert L.dr_workspace_bytes(B.DR_ALGO_REDUCE, 10_000, 1 << 28, ctypes.byref(v), None,
+                                ctypes.byref(size)) == 0
+    assert size.value > small                                  # large tables hold a plan
+    assert L.dr_workspace_bytes(B.DR_ALGO_FOR_EACH, 8, 1 << 28, ctypes.byref(v), None,
+                                ctypes.byref(size)) == 0
+    assert size.value == 256                                   # header only
+    bad_tune = B.dr_tuning(128, 16, 0, 0)
+    assert L.dr_workspace_bytes(B.DR_ALGO_REDUCE, 8, 100, ctypes.byref(v), ctypes.byref(bad_tune),
+                                ctypes.byref(size)) == -2
+    t, keep = _host_table([((A, Bp), (), 10)], 10)
+    init = ctypes.c_double(0.0)
+    # workspace missing, misaligned, too small
+    assert L.dr_transform_reduce(ctypes.byref(t), ctypes.byref(v), 1, ctypes.byref(init), O, None, 0, None,
+                                 None) == -3
+    assert L.dr_transform_reduce(ctypes.byref(t), ctypes.byref(v), 1, ctypes.byref(init), O, 0x40000010,
+                                 1 << 20, None, None) == -3
+    assert L.dr_transform_reduce(ctypes.byref(t), ctypes.byref(v), 1, ctypes.byref(init), O, 0x40000000,
+                                 256, None, None) == -3
+    assert L.dr_transform_reduce(ctypes.byref(t), ctypes.byref(v), 5, ctypes.byref(init), O, 0x40000000,
+                                 1 << 20, None, None) == -1    # unknown acc
+    assert L.dr_transform_reduce(ctypes.byref(t), ctypes.byref(v), 1, None, O, 0x40000000, 1 << 20, None,
+                                 None) == -1                   # NULL init
+    assert L.dr_workspace_init(None, 1024, None) == -3
+    assert L.dr_workspace_init(0x40000010, 1024, None) == -3
+    flags = ctypes.c_uint32(0)
+    assert L.dr_device_status(None, ctypes.byref(flags), None) == -3
+    del keep
+
+
+def test_fused_and_adjoint_argument_checks():
+    L = B.lib()
+    t, keep = _host_table([((A, Bp), (O,), 10)], 10)
+    sv = B.make_view("identity", B.DR_F32)
+    rv = B.make_view("mul", B.DR_F32)
+    init = ctypes.c_double(0.0)
+    assert L.dr_scan_reduce(ctypes.byref(t), ctypes.byref(rv), ctypes.byref(rv), 1, ctypes.byref(init), O,
+                            0, 0x40000000, 1 << 20, None, None) == -2
+    assert L.dr_scan_reduce(ctypes.byref(t), ctypes.byref(sv), ctypes.byref(sv), 1, ctypes.byref(init), O,
+                            0, 0x40000000, 1 << 20, None, None) == -2
+    assert L.dr_scan_reduce(ctypes.byref(t), ctypes.byref(sv), ctypes.byref(rv), 1, ctypes.byref(init), O,
+                            2, 0x40000000, 1 << 20, None, None) == -1
+    assert L.dr_broadcast_mul(ctypes.byref(t), ctypes.byref(rv), None, 2, None, 0, None, None) == -1
+    assert L.dr_broadcast_mul(ctypes.byref(t), ctypes.byref(rv), 0x50000000, 3, None, 0, None, None) == -1
+    vi = B.make_view("mul", B.DR_I32)
+    assert L.dr_broadcast_mul(ctypes.byref(t), ctypes.byref(vi), 0x50000000, 1, None, 0, None, None) == -2
+    del keep
+
+
+def test_tuning_supported_table():
+    L = B.lib()
+    v = B.make_view("mul", B.DR_F32)
+    assert L.dr_tuning_supported(B.DR_ALGO_REDUCE, ctypes.byref(v), B.DR_ACC_COMPENSATED, None) == 1
+    t32 = B.dr_tuning(256, 32, 0, 0)
+    assert L.dr_tuning_supported(B.DR_ALGO_REDUCE, ctypes.byref(v), B.DR_ACC_COMPENSATED, ctypes.byref(t32)) == 1
+    t7 = B.dr_tuning(256, 7, 0, 0)
+    assert L.dr_tuning_supported(B.DR_ALGO_REDUCE, ctypes.byref(v), B.DR_ACC_COMPENSATED, ctypes.byref(t7)) == 0
+    vs = B.make_view("identity", B.DR_I32)
+    assert L.dr_tuning_supported(B.DR_ALGO_SCAN, ctypes.byref(vs), B.DR_I64, None) == 1
+    assert L.dr_tuning_supported(B.DR_ALGO_SCAN, ctypes.byref(vs), B.DR_F32, None) == 0

@@ -1,0 +1,328 @@
+"""GPU parity: every entry point of the C ABI against the CPU oracle on the
+same seeded inputs, at sizes that span several tiles with ragged tails,
+with empty and one-element segments, small (planned in every launch) and
+large (planned by dr_plan) tables, and segments whose starts are aligned,
+misaligned, and misaligned relative to each other.
+
+Bars: bit-exact for integers, for_each and the adjoint broadcast; the
+derived error bounds of tests/gpu_util.py for floating-point sums."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2406_00158_amd import binding as B
+from paper_2406_00158_amd import inputs as I
+
+from gpu_util import (U32, U64, announce, dev, dev_to_np, empty_like_segments, gather, np_to_dev, place,
+                      reduce_bound, scan_fp32_bound)
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+OR_DT = {B.DR_I32: O.I32, B.DR_F32: O.F32, B.DR_BF16: O.BF16, B.DR_F64: O.F64, B.DR_I64: O.I64}
+OR_OP = {B.DR_OP_IDENTITY: O.IDENTITY, B.DR_OP_SQUARE: O.SQUARE, B.DR_OP_MUL: O.MUL, B.DR_OP_AXPY: O.AXPY}
+
+# segmentations: (name, lengths)
+SEGMENTATIONS = [
+    ("one_small", [1000]),
+    ("tile_edges", [4095, 4096, 4097, 1, 0, 8191]),
+    ("ragged16", I.lengths_dirichlet(150_001, 16, 1.0, 77)),
+    ("with_empties", [0, 3, 0, 0, 20000, 1, 0, 33333, 2]),
+    ("many_rows", [(k * 37) % 1500 for k in range(130)]),     # > 64 rows: planned by dr_plan
+]
+
+
+def _values(dtype, n, seed):
+    if dtype == B.DR_I32:
+        return I.ints_0_100(n, seed) - 50
+    x = I.normal_f32(n, seed)
+    if dtype == B.DR_BF16:
+        return I.bf16_bits(x)
+    if dtype == B.DR_F64:
+        return x.astype(np.float64) * (1 + 1e-9 * I.uniform_f32(n, seed + 1).astype(np.float64))
+    return x
+
+
+def _table(arrays, lengths, layout, outs=(), mode="concat", offsets=None):
+    offsets = offsets or [0] * len(arrays)
+    ins = [place(a, lengths, layout, off) for a, off in zip(arrays, offsets)]
+    return B.segments(ins, list(outs), mode=mode), ins
+
+
+LAYOUTS = [("separate", None), ("carved", [0, 0]), ("carved_skew", [1, 3])]
+
+
+# --- for_each -------------------------------------------------------------------
+
+FOR_EACH_CASES = [(B.DR_F32, B.DR_F32), (B.DR_BF16, B.DR_F32), (B.DR_F64, B.DR_F64), (B.DR_I32, B.DR_I32),
+                  (B.DR_I32, B.DR_I64)]
+
+
+@pytest.mark.parametrize("seg_name,lengths", SEGMENTATIONS)
+@pytest.mark.parametrize("in_dt,out_dt", FOR_EACH_CASES)
+@pytest.mark.parametrize("op", [B.DR_OP_IDENTITY, B.DR_OP_SQUARE, B.DR_OP_MUL, B.DR_OP_AXPY])
+def test_for_each(seg_name, lengths, in_dt, out_dt, op):
+    layout, offs = LAYOUTS[(len(lengths) + op) % len(LAYOUTS)]
+    announce("for_each", seg_name, in_dt, out_dt, op, layout)
+    n = sum(lengths)
+    x, y = _values(in_dt, n, 1), _values(in_dt, n, 2)
+    if in_dt == B.DR_I32:
+        x = x * 40000                                      # squares and products wrap int32
+    alpha = 3.0
+    outs = empty_like_segments(lengths, B.TORCH_DTYPE[out_dt], "separate")
+    arity = B.OP_ARITY[op]
+    tab, _ = _table([x, y][:arity], lengths, layout, outs=[outs], offsets=(offs or [0, 0])[:arity])
+    B.dr_for_each(tab, B.make_view(op, in_dt, alpha), out_dt)
+    got = gather(outs)
+    want = np.concatenate(O.for_each(I.split(x, lengths), I.split(y, lengths) if arity == 2 else None,
+                                     OR_DT[in_dt], OR_OP[op], OR_DT[out_dt], alpha=alpha))
+    assert got.dtype == want.dtype
+    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+
+
+def test_for_each_in_place():
+    announce("for_each in place")
+    lengths = [5000, 0, 12345]
+    x = _values(B.DR_F32, sum(lengths), 3)
+    segs = place(x, lengths, "separate")
+    tab = B.segments([segs], [segs])
+    B.dr_for_each(tab, B.make_view("square", B.DR_F32), B.DR_F32)
+    want = np.concatenate(O.for_each(I.split(x, lengths), None, O.F32, O.SQUARE, O.F32))
+    assert np.array_equal(gather(segs), want)
+
+
+# --- transform_reduce -------------------------------------------------------------
+
+REDUCE_DTYPES = [B.DR_F32, B.DR_BF16, B.DR_F64, B.DR_I32]
+
+
+@pytest.mark.parametrize("seg_name,lengths", SEGMENTATIONS)
+@pytest.mark.parametrize("in_dt", REDUCE_DTYPES)
+@pytest.mark.parametrize("op", [B.DR_OP_IDENTITY, B.DR_OP_SQUARE, B.DR_OP_MUL, B.DR_OP_AXPY])
+@pytest.mark.parametrize("mode", ["concat", "batch"])
+@pytest.mark.parametrize("acc", ["compensated", "plain"])
+def test_transform_reduce(seg_name, lengths, in_dt, op, mode, acc):
+    if in_dt in (B.DR_I32, B.DR_F64) and acc == "plain":
+        pytest.skip("integer and binary64 reductions have one accumulation")
+    layout, offs = LAYOUTS[(len(lengths) + op) % len(LAYOUTS)]
+    announce("reduce", seg_name, in_dt, op, mode, acc, layout)
+    n = sum(lengths)
+    x, y = _values(in_dt, n, 11), _values(in_dt, n, 12)
+    arity = B.OP_ARITY[op]
+    alpha = 3.0
+    tab, _ = _table([x, y][:arity], lengths, layout, mode=mode, offsets=(offs or [0, 0])[:arity])
+    nres = len(lengths) if mode == "batch" else 1
+    is_int = in_dt == B.DR_I32
+    init = 7 if is_int else 0.25
+    res = torch.full((nres,), -1, dtype=torch.int64 if is_int else torch.float64, device=dev())
+    B.dr_transform_reduce(tab, B.make_view(op, in_dt, alpha), B.ACCS[acc], init, res)
+    got = dev_to_np(res)
+    want, mag = O.reduce(I.split(x, lengths), I.split(y, lengths) if arity == 2 else None, OR_DT[in_dt],
+                         OR_OP[op], mode=O.BATCH if mode == "batch" else O.CONCAT, init=init, alpha=alpha)
+    if is_int:
+        assert np.array_equal(got, want)
+        return
+    tiles = max(1, n // 4096 + len(lengths))
+    ebytes = {B.DR_F32: 4, B.DR_BF16: 2, B.DR_F64: 8}[in_dt]
+    for g, w, a in zip(got, want, mag):
+        bound = reduce_bound(a + abs(init), acc, in_bytes=ebytes, tiles=tiles)
+        assert abs(g - w) <= bound, (g, w, bound)
+
+
+def test_reduce_is_deterministic_and_reusable():
+    announce("reduce determinism")
+    lengths = I.lengths_dirichlet(3_000_000, 16, 1.0, 5)
+    x, y = I.mixture_f32(sum(lengths), 5), I.mixture_f32(sum(lengths), 6)
+    tab, _ = _table([x, y], lengths, "separate")
+    ws = B.Workspace(dev())
+    out = []
+    for _ in range(5):
+        res = torch.zeros(1, dtype=torch.float64, device=dev())
+        B.dr_transform_reduce(tab, B.make_view("mul", B.DR_F32), B.DR_ACC_COMPENSATED, 0.0, res, workspace=ws)
+        out.append(res.item())
+    assert len(set(out)) == 1
+    want, mag = O.reduce(I.split(x, lengths), I.split(y, lengths), O.F32, O.MUL)
+    assert abs(out[0] - want[0]) <= reduce_bound(mag[0], "compensated", tiles=800)
+    assert ws.device_status() == 0
+
+
+def test_reduce_empty_range_gives_init():
+    announce("reduce empty")
+    tab = B.segments([[torch.empty(0, device=dev()), torch.empty(0, device=dev())]], mode="batch")
+    res = torch.zeros(2, dtype=torch.float64, device=dev())
+    B.dr_transform_reduce(tab, B.make_view("identity", B.DR_F32), 1, 2.5, res)
+    assert dev_to_np(res).tolist() == [2.5, 2.5]
+    tab = B.segments([[torch.empty(0, dtype=torch.int32, device=dev())]], mode="concat")
+    res = torch.zeros(1, dtype=torch.int64, device=dev())
+    B.dr_transform_reduce(tab, B.make_view("identity", B.DR_I32), 1, -9, res)
+    assert dev_to_np(res).tolist() == [-9]
+
+
+# --- inclusive_scan ---------------------------------------------------------------
+
+SCAN_CASES = [(B.DR_I32, B.DR_I64), (B.DR_I32, B.DR_I32), (B.DR_F32, B.DR_F32), (B.DR_BF16, B.DR_F32),
+              (B.DR_F64, B.DR_F64)]
+
+
+@pytest.mark.parametrize("seg_name,lengths", SEGMENTATIONS)
+@pytest.mark.parametrize("in_dt,out_dt", SCAN_CASES)
+@pytest.mark.parametrize("mode", ["concat", "batch"])
+@pytest.mark.parametrize("reverse", [False, True])
+def test_inclusive_scan(seg_name, lengths, in_dt, out_dt, mode, reverse):
+    op = B.DR_OP_IDENTITY
+    layout, offs = LAYOUTS[(len(lengths) + int(reverse)) % len(LAYOUTS)]
+    announce("scan", seg_name, in_dt, out_dt, mode, reverse, layout)
+    n = sum(lengths)
+    x = _values(in_dt, n, 21)
+    if in_dt == B.DR_I32 and out_dt == B.DR_I32:
+        x = x * 10_000_000                                  # the int32 output wraps
+    outs = empty_like_segments(lengths, B.TORCH_DTYPE[out_dt], "separate")
+    tab, _ = _table([x], lengths, layout, outs=[outs], mode=mode, offsets=(offs or [0])[:1])
+    B.dr_inclusive_scan(tab, B.make_view(op, in_dt), out_dt, B.DR_SCAN_REVERSE if reverse else 0)
+    got = gather(outs)
+    omode = O.BATCH if mode == "batch" else O.CONCAT
+    if in_dt == B.DR_I32:
+        want = np.concatenate(O.scan(I.split(x, lengths), None, O.I32, O.IDENTITY, mode=omode,
+                                     reverse=reverse, out_dtype=OR_DT[out_dt]))
+        assert np.array_equal(got, want)
+        return
+    ref, absp = O.scan(I.split(x, lengths), None, OR_DT[in_dt], O.IDENTITY, mode=omode, reverse=reverse,
+                       want_abs=True)
+    ref, absp = np.concatenate(ref), np.concatenate(absp)
+    if in_dt == B.DR_F64:
+        bound = 40 * U64 * absp + U64 * np.abs(ref)
+    else:
+        bound = scan_fp32_bound(ref, absp, tiles=n // 4096 + len(lengths))
+    err = np.abs(got.astype(np.float64) - ref)
+    assert np.all(err <= bound), (err.max(), int(np.argmax(err - bound)))
+
+
+@pytest.mark.parametrize("op", [B.DR_OP_SQUARE, B.DR_OP_MUL, B.DR_OP_AXPY])
+def test_scan_of_views(op):
+    lengths = [7000, 1, 0, 9000]
+    announce("scan view", op)
+    n = sum(lengths)
+    x, y = _values(B.DR_I32, n, 31), _values(B.DR_I32, n, 32)
+    arity = B.OP_ARITY[op]
+    outs = empty_like_segments(lengths, torch.int64)
+    tab, _ = _table([x, y][:arity], lengths, "separate", outs=[outs])
+    B.dr_inclusive_scan(tab, B.make_view(op, B.DR_I32, 3.0), B.DR_I64)
+    want = np.concatenate(O.scan(I.split(x, lengths), I.split(y, lengths) if arity == 2 else None, O.I32,
+                                 OR_OP[op], alpha=3.0))
+    assert np.array_equal(gather(outs), want)
+
+
+def test_scan_ones_closed_form():
+    n = (1 << 24) + 12345                                    # past the binary32 carry limit
+    announce("scan ones", n)
+    lengths = I.lengths_dirichlet(n, 16, 1.0, 1)
+    ones = torch.ones(n, dtype=torch.float32, device=dev())
+    out = torch.empty(n, dtype=torch.float32, device=dev())
+    ins, outs, o = [], [], 0
+    for L in lengths:
+        ins.append(ones[o:o + L])
+        outs.append(out[o:o + L])
+        o += L
+    tab = B.segments([ins], [outs])
+    B.dr_inclusive_scan(tab, B.make_view("identity", B.DR_F32), B.DR_F32)
+    want = np.arange(1, n + 1, dtype=np.float64).astype(np.float32)
+    assert np.array_equal(dev_to_np(out), want)
+    # binary32 carries are exact here too: every tile sum of ones is a
+    # multiple of the tile size, exactly representable, and each output is
+    # one rounding of the exact value
+    B.dr_inclusive_scan(tab, B.make_view("identity", B.DR_F32), B.DR_F32, B.DR_SCAN_CARRY_F32)
+    assert np.array_equal(dev_to_np(out), want)
+
+
+def test_scan_in_place_and_reuse():
+    announce("scan in place")
+    lengths = [30000, 0, 4096, 77]
+    x = _values(B.DR_F32, sum(lengths), 41)
+    segs = place(x, lengths, "separate")
+    tab = B.segments([segs], [segs])
+    ws = B.Workspace(dev())
+    B.dr_inclusive_scan(tab, B.make_view("identity", B.DR_F32), B.DR_F32, workspace=ws)
+    ref, absp = O.scan(I.split(x, lengths), None, O.F32, O.IDENTITY, want_abs=True)
+    ref, absp = np.concatenate(ref), np.concatenate(absp)
+    assert np.all(np.abs(gather(segs) - ref) <= scan_fp32_bound(ref, absp, tiles=20))
+    # many launches on one workspace (epoch tags advance every launch)
+    y = _values(B.DR_I32, sum(lengths), 42)
+    ysegs = place(y, lengths, "separate")
+    outs = empty_like_segments(lengths, torch.int64)
+    tab2 = B.segments([ysegs], [outs])
+    want = np.concatenate(O.scan(I.split(y, lengths), None, O.I32, O.IDENTITY))
+    for _ in range(20):
+        B.dr_inclusive_scan(tab2, B.make_view("identity", B.DR_I32), B.DR_I64, workspace=ws)
+    assert np.array_equal(gather(outs), want)
+    assert ws.device_status() == 0
+
+
+# --- fused scan + reduce (batched) ------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["batch", "concat"])
+@pytest.mark.parametrize("reverse", [False, True])
+def test_scan_reduce_fused(mode, reverse):
+    lengths = I.lengths_loguniform(300, 1 << 14, 1 << 20, 9)
+    announce("scan_reduce", mode, reverse, len(lengths))
+    n = sum(lengths)
+    x, y = I.normal_f32(n, 51), I.normal_f32(n, 52)
+    outs = empty_like_segments(lengths, torch.float32)
+    tab, _ = _table([x, y], lengths, "carved", outs=[outs], mode=mode, offsets=[0, 0])
+    nres = len(lengths) if mode == "batch" else 1
+    res = torch.zeros(nres, dtype=torch.float64, device=dev())
+    B.dr_scan_reduce(tab, B.make_view("identity", B.DR_F32), B.make_view("mul", B.DR_F32),
+                     B.DR_ACC_COMPENSATED, 0.0, res, B.DR_SCAN_REVERSE if reverse else 0)
+    omode = O.BATCH if mode == "batch" else O.CONCAT
+    ref, absp = O.scan(I.split(x, lengths), None, O.F32, O.IDENTITY, mode=omode, reverse=reverse, want_abs=True)
+    ref, absp = np.concatenate(ref), np.concatenate(absp)
+    err = np.abs(gather(outs).astype(np.float64) - ref)
+    assert np.all(err <= scan_fp32_bound(ref, absp, tiles=n // 4096 + len(lengths)))
+    want, mag = O.reduce(I.split(x, lengths), I.split(y, lengths), O.F32, O.MUL, mode=omode)
+    got = dev_to_np(res)
+    for g, w, a in zip(got, want, mag):
+        assert abs(g - w) <= reduce_bound(a, "compensated", tiles=n // 4096 + len(lengths))
+
+
+# --- adjoint broadcast multiply ----------------------------------------------------------
+
+@pytest.mark.parametrize("in_dt", [B.DR_F32, B.DR_BF16, B.DR_F64])
+@pytest.mark.parametrize("op", [B.DR_OP_MUL, B.DR_OP_SQUARE, B.DR_OP_AXPY, B.DR_OP_IDENTITY])
+@pytest.mark.parametrize("mode", ["concat", "batch"])
+def test_broadcast_mul(in_dt, op, mode):
+    lengths = [3000, 0, 1, 5000, 4096] if mode == "concat" else [(k * 53) % 700 for k in range(70)]
+    announce("broadcast_mul", in_dt, op, mode)
+    n = sum(lengths)
+    x, y = _values(in_dt, n, 61), _values(in_dt, n, 62)
+    arity = B.OP_ARITY[op]
+    odt = torch.float64 if in_dt == B.DR_F64 else torch.float32
+    ng = arity
+    grads = [empty_like_segments(lengths, odt) for _ in range(ng)]
+    tab, _ = _table([x, y][:arity], lengths, "separate", outs=grads, mode=mode)
+    nres = len(lengths) if mode == "batch" else 1
+    g = np_to_dev(I.normal_f32(nres, 63).astype(np.float64))
+    B.dr_broadcast_mul(tab, B.make_view(op, in_dt, 2.5), g, ng)
+    for which in range(ng):
+        want = np.concatenate(O.reduce_grad(I.split(x, lengths), I.split(y, lengths) if arity == 2 else None,
+                                            OR_DT[in_dt], OR_OP[op], dev_to_np(g), which,
+                                            mode=O.BATCH if mode == "batch" else O.CONCAT, alpha=2.5))
+        got = gather(grads[which])
+        assert np.array_equal(got, want.astype(got.dtype))
+
+
+# --- device-side fault flags (forced from the host; kernels exit normally) -------------
+
+def test_device_flags_bad_table_without_host_mirror():
+    announce("device flags")
+    x = torch.ones(100, device=dev())
+    out = torch.empty(100, device=dev())
+    tab = B.segments([[x]], [[out]])
+    tab.total_length = 99                  # lie about the total; host mirror not passed
+    ws = B.Workspace(dev())
+    B.dr_inclusive_scan(tab, B.make_view("identity", B.DR_F32), B.DR_F32, workspace=ws, host_check=False)
+    assert ws.device_status() & 1
+    assert ws.device_status() == 0         # cleared by the read
+    tab.total_length = 100
+    B.dr_inclusive_scan(tab, B.make_view("identity", B.DR_F32), B.DR_F32, workspace=ws)
+    assert np.array_equal(dev_to_np(out), np.arange(1, 101, dtype=np.float32))
+    assert ws.device_status() == 0
