@@ -260,9 +260,11 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
  * Fused inclusive_scan + transform_reduce over the same rows in one launch,
  * every input element read once: out[0] receives the inclusive scan of the
  * scan view (identity of in[0]), and `result` the reduction of the reduce
- * view (op over in[0], in[1]); both per segment in BATCH mode. Types as for
- * the two calls: F32 in, F32 scan out, binary64 results. `init` is a host
- * double.
+ * view (mul over in[0], in[1]); both per segment in BATCH mode. Types:
+ * F32 in -> F32 scan out (binary64 carries) and a binary64 result with
+ * `acc` accumulation; F64 in -> F64 scan out and result (`acc` ignored).
+ * `init` is a host double. This is the batched form: thousands of ragged
+ * ranges in BATCH mode are one launch (capturable in a hipGraph).
  */
 dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view,
                          const dr_view* reduce_view, int32_t acc, const void* init,

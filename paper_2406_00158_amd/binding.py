@@ -136,18 +136,15 @@ def make_tuning(items_per_thread: int | None) -> dr_tuning | None:
 @dataclass
 class Table:
     """A segment table: row k holds segment k of every zipped input and of
-    every output stream, and its length. The tensors are kept alive here."""
-    inputs: list
-    outputs: list
+    every output stream, and its length. `keep` holds the tensors alive when
+    the table was built with keep_alive=True."""
+    n_segments: int
     mode: int
     device: torch.device
     host_rows: ctypes.Array = field(repr=False, default=None)
     dev_rows: torch.Tensor = field(repr=False, default=None)
     total_length: int = 0
-
-    @property
-    def n_segments(self) -> int:
-        return len(self.inputs[0]) if self.inputs else 0
+    keep: list = field(repr=False, default_factory=list)
 
     def c_table(self, host_check: bool = True) -> dr_table:
         rows = self.dev_rows.data_ptr() if self.n_segments else None
@@ -155,12 +152,15 @@ class Table:
         return dr_table(rows, host, self.n_segments, self.total_length, self.mode, 0)
 
 
-def segments(inputs, outputs=None, mode: int | str = DR_MODE_CONCAT, device=None) -> Table:
+def segments(inputs, outputs=None, mode: int | str = DR_MODE_CONCAT, device=None,
+             keep_alive: bool = True) -> Table:
     """Build a table from per-segment tensors.
 
     inputs:  list over zipped inputs of lists over segments of 1-D tensors
              (all inputs must have the same number of segments and lengths).
     outputs: optional list (at most 2) of such lists for output streams.
+    keep_alive: hold references to the tensors (otherwise the caller must
+             keep them alive while the table is used).
     """
     mode = MODES[mode] if isinstance(mode, str) else mode
     outputs = outputs or []
@@ -193,7 +193,8 @@ def segments(inputs, outputs=None, mode: int | str = DR_MODE_CONCAT, device=None
         total += n
     raw = np.frombuffer(bytes(host), dtype=np.uint8)[: 64 * m]
     dev = torch.from_numpy(raw.copy()).to(device) if m else torch.empty(0, dtype=torch.uint8, device=device)
-    return Table(list(inputs), list(outputs), mode, device, host, dev, total)
+    keep = [list(inputs), list(outputs)] if keep_alive else []
+    return Table(m, mode, device, host, dev, total, keep)
 
 
 # --- workspace ----------------------------------------------------------------

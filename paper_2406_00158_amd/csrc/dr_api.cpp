@@ -420,10 +420,12 @@ dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view, const 
     if (s) return s;
     s = check_view(reduce_view, false);
     if (s) return s;
-    if (scan_view->op != DR_OP_IDENTITY || scan_view->in_dtype != DR_F32)
-        return fail(DR_ERR_UNSUPPORTED, "fused scan: the scan view must be identity over binary32 in[0]");
-    if (reduce_view->in_dtype != DR_F32 || reduce_view->op != DR_OP_MUL)
-        return fail(DR_ERR_UNSUPPORTED, "fused scan: the reduce view must be mul over binary32 in[0], in[1]");
+    const int in = scan_view->in_dtype;
+    if (scan_view->op != DR_OP_IDENTITY || (in != DR_F32 && in != DR_F64))
+        return fail(DR_ERR_UNSUPPORTED, "fused scan: the scan view must be identity over binary32/64 in[0]");
+    if (reduce_view->in_dtype != in || reduce_view->op != DR_OP_MUL)
+        return fail(DR_ERR_UNSUPPORTED, "fused scan: the reduce view must be mul over in[0], in[1] of the "
+                                        "scanned type");
     if (acc != DR_ACC_PLAIN && acc != DR_ACC_COMPENSATED) return fail(DR_ERR_INVALID_ARG, "unknown acc %d", acc);
     if (flags & ~(uint32_t)DR_SCAN_REVERSE) return fail(DR_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
     if (!init) return fail(DR_ERR_INVALID_ARG, "init is NULL");
@@ -431,9 +433,9 @@ dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view, const 
         return fail(DR_ERR_INVALID_ARG, "result is NULL");
     Prepared p;
     int items;
-    s = prepare(table, DR_ALGO_SCAN_REDUCE, DR_F32, DR_F32, 2, 1, tuning, ws, ws_bytes, true, true, p, items);
+    s = prepare(table, DR_ALGO_SCAN_REDUCE, in, in, 2, 1, tuning, ws, ws_bytes, true, true, p, items);
     if (s) return s;
-    LaunchFn fn = find_scan_reduce(DR_F32, reduce_view->op, acc, items);
+    LaunchFn fn = find_scan_reduce(in, reduce_view->op, acc, items);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "fused scan kernel not built for this combination");
     p.a.flags = flags;
     p.a.result = result;

@@ -175,7 +175,16 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
 
     // fused reduction of the second view (not order-sensitive)
     double rpart_thread = 0.0;
-    if constexpr (FUSED) {
+    if constexpr (FUSED && IDT == DR_F64) {
+        double rs = 0.0;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                rs += view_apply<ROP, double>(decode<IDT>(x[s].e[e]), decode<IDT>(y[s].e[e]), 0.0);
+        }
+        rpart_thread = rs;
+    } else if constexpr (FUSED) {
         float rs = 0.0f, rc = 0.0f;
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
@@ -310,7 +319,10 @@ LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items) {
 }
 
 LaunchFn find_scan_reduce(int in_dt, int reduce_op, int acc, int items) {
-    if (in_dt != DR_F32 || items != 16) return nullptr;
+    if (items != 16) return nullptr;
+    if (in_dt == DR_F64 && reduce_op == DR_OP_MUL)
+        return launch_scan<DR_F64, DR_F64, DR_OP_IDENTITY, true, true, DR_OP_MUL, DR_ACC_PLAIN, 16>;
+    if (in_dt != DR_F32) return nullptr;
     if (reduce_op == DR_OP_MUL && acc == DR_ACC_COMPENSATED)
         return launch_scan<DR_F32, DR_F32, DR_OP_IDENTITY, true, true, DR_OP_MUL, DR_ACC_COMPENSATED, 16>;
     if (reduce_op == DR_OP_MUL && acc == DR_ACC_PLAIN)
