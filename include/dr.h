@@ -185,7 +185,9 @@ const char* dr_status_string(dr_status status);
 /* Detail of the last error returned on the calling thread ("" if none). */
 const char* dr_last_error(void);
 
-/* 1 if (algo, view, out_dtype, tuning) has a built kernel, else 0. */
+/* 1 if (algo, view, out_dtype, tuning) has a built kernel, else 0. For
+ * DR_ALGO_REDUCE `out_dtype` carries the dr_acc instead; for
+ * DR_ALGO_SCAN_REDUCE the reduce view is mul, compensated. */
 int dr_tuning_supported(int32_t algo, const dr_view* view, int32_t out_dtype,
                         const dr_tuning* tuning);
 

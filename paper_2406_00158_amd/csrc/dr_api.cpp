@@ -199,13 +199,15 @@ WsLayout layout_for(int algo, int64_t m, int64_t tmax) {
     L.off_tile = off;
     off += align256((uint64_t)tmax * L.tile_words * 8);
     const uint64_t ngroups = uses_combine(algo) ? (uint64_t)(tmax / kGroupTiles + m + 2) : 0;
+    L.ngroups = ngroups;
     L.off_gcnt = off;
-    off += align256(ngroups * 8);
+    off += align256(ngroups * 4);
     L.off_gpart = off;
     off += align256(ngroups * 16);
     const uint64_t nunits = uses_combine(algo) ? (uint64_t)std::max<int64_t>(m, 1) : 0;
+    L.nunits = nunits;
     L.off_ucnt = off;
-    off += align256(nunits * 8);
+    off += align256(nunits * 4);
     L.bytes = off;
     return L;
 }

@@ -3,15 +3,15 @@
 //
 // The paper's reduce computes a partial per segment and adds the partials
 // once all are complete (section 4.3, "reduce"; Algorithm 3). Here a
-// "unit" is what one result covers: one segment's tiles (BATCH), or the
-// workgroups of the launch, each holding the sum of its own tiles (CONCAT).
+// "unit" is what one result covers: one segment's tiles (BATCH), or all the
+// tiles of the launch (CONCAT), and its members are those tiles.
 // Each member publishes its partial; the last member to arrive in a group of
 // 64 consecutive members sums the group's partials, and the last group to
 // arrive sums the group sums and adds `init`. Arrivals are counted with
-// tagged agent-scope counters, but the sums always run in member order over
-// a fixed tree, so a result does not depend on the order in which
-// workgroups happen to finish. Everything is tagged with the launch epoch,
-// so nothing needs clearing before the next launch.
+// agent-scope fetch-and-add on counters the launch prologue zeroed; the sums
+// always run in member order over a fixed tree, so a result does not depend
+// on the order in which workgroups happen to finish. Partials carry the
+// launch's epoch tag: a reader spins until the one it needs is visible.
 #pragma once
 
 #include <type_traits>
@@ -56,69 +56,60 @@ __device__ __forceinline__ void fill_empty_after(const LaunchArgs& a, int64_t k)
 
 // Member `idx` (0-based within its unit of `count` members, whose partial
 // words start at member slot `base` of the tile-word array) publishes
-// `partial` (held by thread 0) and, if it completes its group or the unit,
-// combines. `slot0` is the unit's first group slot. Whole workgroup.
+// `partial` (held by lane 0) and, if it completes its group or the unit,
+// combines. `slot0` is the unit's first group slot. Called by ONE whole wave
+// (the other waves of the workgroup need not wait for it).
 template <class P>
 __device__ __forceinline__ void combine_member(const LaunchArgs& a, uint32_t tag, int64_t unit, int64_t base,
                                                int64_t idx, int64_t count, int64_t slot0, P partial) {
-    __shared__ int s_last;
     const int64_t gi = idx / kGroupTiles;
     const int64_t g0 = gi * kGroupTiles;
     const int64_t gn = (count - g0) < kGroupTiles ? (count - g0) : kGroupTiles;
     const int64_t ngroups = (count + kGroupTiles - 1) / kGroupTiles;
     uint64_t* tw = (uint64_t*)(a.ws + a.lay.off_tile);
-    uint64_t* gcnt = (uint64_t*)(a.ws + a.lay.off_gcnt);
+    uint32_t* gcnt = (uint32_t*)(a.ws + a.lay.off_gcnt);
     uint64_t* gpart = (uint64_t*)(a.ws + a.lay.off_gpart);
-    uint64_t* ucnt = (uint64_t*)(a.ws + a.lay.off_ucnt);
+    uint32_t* ucnt = (uint32_t*)(a.ws + a.lay.off_ucnt);
     const int64_t TW = a.lay.tile_words, PW = a.lay.part_word;
+    const int l = lane_id();
 
-    if (threadIdx.x == 0) {
+    int last_in_group = 0;
+    if (l == 0) {
         tagged_store(tw + (base + idx) * TW + PW, tag, to_bits(partial));
-        s_last = tagged_count(gcnt + slot0 + gi, tag) == (uint32_t)(gn - 1);
+        last_in_group = atomic_add32(gcnt + slot0 + gi, 1u) == (uint32_t)(gn - 1);
     }
-    __syncthreads();
-    if (s_last && threadIdx.x < 64) {
-        // wave 0: sum the group's partials in member order
-        const int l = lane_id();
-        P v = (P)0;
-        if (l < gn) v = wait_tagged<P>(a, tw + (base + g0 + l) * TW + PW, tag);
-        const P gsum = wave_sum(v);
-        if (ngroups == 1) {
-            if (l == 0) write_result<P>(a, unit, gsum);
-        } else {
-            int last = 0;
-            if (l == 0) {
-                tagged_store(gpart + (slot0 + gi) * 2, tag, to_bits(gsum));
-                last = tagged_count(ucnt + unit, tag) == (uint32_t)(ngroups - 1);
-            }
-            last = readlane(last, 0);
-            if (last) {
-                P acc = (P)0;
-                for (int64_t g = l; g < ngroups; g += 64) acc += wait_tagged<P>(a, gpart + (slot0 + g) * 2, tag);
-                const P tot = wave_sum(acc);
-                if (l == 0) write_result<P>(a, unit, tot);
-            }
-        }
+    if (!readlane(last_in_group, 0)) return;
+    // the group is complete: sum its partials in member order
+    P v = (P)0;
+    if (l < gn) v = wait_tagged<P>(a, tw + (base + g0 + l) * TW + PW, tag);
+    const P gsum = wave_sum(v);
+    if (ngroups == 1) {
+        if (l == 0) write_result<P>(a, unit, gsum);
+        return;
     }
-    __syncthreads();
+    int last = 0;
+    if (l == 0) {
+        tagged_store(gpart + (slot0 + gi) * 2, tag, to_bits(gsum));
+        last = atomic_add32(ucnt + unit, 1u) == (uint32_t)(ngroups - 1);
+    }
+    if (!readlane(last, 0)) return;
+    P acc = (P)0;
+    for (int64_t g = l; g < ngroups; g += 64) acc += wait_tagged<P>(a, gpart + (slot0 + g) * 2, tag);
+    const P tot = wave_sum(acc);
+    if (l == 0) write_result<P>(a, unit, tot);
 }
 
 // BATCH: tile t of segment si publishes its partial; the segment's last
 // group writes result[k]. Group slots of segment k start at first/64 + k.
+// One whole wave.
 template <class P>
 __device__ __forceinline__ void combine_tile_batch(const LaunchArgs& a, uint32_t tag, int64_t t,
                                                    const SegInfo& si, P partial) {
-    if (threadIdx.x == 0 && t == si.first) {
+    if (lane_id() == 0 && t == si.first) {
         if (t == 0) fill_empty_after<P>(a, -1);
         fill_empty_after<P>(a, si.k);
     }
     combine_member<P>(a, tag, si.k, si.first, t - si.first, si.ntiles, si.first / kGroupTiles + si.k, partial);
-}
-
-// CONCAT: every workgroup publishes the sum of its tiles; result[0].
-template <class P>
-__device__ __forceinline__ void combine_grid(const LaunchArgs& a, uint32_t tag, P partial) {
-    combine_member<P>(a, tag, 0, 0, blockIdx.x, gridDim.x, 0, partial);
 }
 
 // BATCH launch with no tiles at all: every result is `init`.

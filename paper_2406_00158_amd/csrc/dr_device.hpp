@@ -218,25 +218,11 @@ __device__ __forceinline__ void flag_error(uint8_t* ws, uint32_t bit) {
 }
 
 // Tag of the running launch: the prologue kernel that precedes every
-// launch using tags has already bumped the workspace epoch, so a plain load
-// (ordered after the prologue by the stream) gives every workgroup the same
-// value without any atomic.
+// launch using tags has already bumped the workspace epoch (and zeroed the
+// launch's arrival counters), so a plain load, ordered after the prologue by
+// the stream, gives every workgroup the same value without any atomic.
 __device__ __forceinline__ uint32_t begin_launch(const uint8_t* ws) {
     return epoch_tag(((const Header*)ws)->epoch);
-}
-
-// Arrival counter that needs no reset between launches: the word holds
-// (tag << 32) | count and a count under another tag reads as 0. Returns the
-// number of arrivals before this one in the current launch.
-__device__ __forceinline__ uint32_t tagged_count(uint64_t* c, uint32_t tag) {
-    uint64_t old = atomic_ld(c);
-    while (true) {
-        const uint32_t cnt = ((uint32_t)(old >> 32) == tag) ? (uint32_t)old : 0u;
-        const uint64_t nw = ((uint64_t)tag << 32) | (uint64_t)(cnt + 1u);
-        if (__hip_atomic_compare_exchange_strong(c, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT))
-            return cnt;
-    }
 }
 
 // ---------------------------------------------------------------------------

@@ -48,10 +48,12 @@ struct WsLayout {
     uint64_t off_plan_first;   // tagged [m + 1]: first tile of each segment (large tables)
     uint64_t off_plan_tseg;    // tagged [tmax]: segment of each tile (large tables)
     uint64_t off_tile;         // [tmax * tile_words]: per-tile (or per-workgroup) tagged words
-    uint64_t off_gcnt;         // tagged counters [ngroups]: arrivals per combine group
+    uint64_t off_gcnt;         // uint32 [ngroups]: arrivals per combine group (zeroed by the prologue)
     uint64_t off_gpart;        // [ngroups * 2]: tagged group partials
-    uint64_t off_ucnt;         // tagged counters [nunits]: arrived groups per result
+    uint64_t off_ucnt;         // uint32 [nunits]: arrived groups per result (zeroed by the prologue)
     uint64_t bytes;            // total size
+    uint64_t ngroups;          // counters at off_gcnt
+    uint64_t nunits;           // counters at off_ucnt
     int32_t tile_words;        // 64-bit words per tile
     int32_t part_word;         // first word of the reduce partial inside a tile's words
 };
@@ -83,8 +85,9 @@ struct LaunchArgs {
 // tags are preceded by the epoch prologue).
 typedef hipError_t (*LaunchFn)(const LaunchArgs& a, int64_t grid, hipStream_t stream);
 
-// The one-thread prologue of every launch that uses tags: epoch + 1.
-hipError_t launch_epoch_bump(uint8_t* ws, hipStream_t stream);
+// The prologue of every launch that uses tags: epoch + 1, and the launch's
+// arrival counters (if any) set to 0.
+hipError_t launch_prologue(const LaunchArgs& a, hipStream_t stream);
 
 // Kernel lookup. `items` is the elements per thread of the tile. Each
 // returns nullptr when the combination is not built.

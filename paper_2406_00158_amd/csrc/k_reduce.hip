@@ -120,7 +120,6 @@ __device__ __forceinline__ partial_t<IDT> tile_partial(const LaunchArgs& a, cons
         if (threadIdx.x == 0)
             for (int i = 0; i < WAVES; ++i) part += s_wave[i];
     }
-    __syncthreads();   // s_wave is reused by the next tile
     return part;
 }
 
@@ -138,6 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(LaunchArgs a) {
         SegInfo si;
         if (!tm.find(a, t, si)) return;
         const P part = tile_partial<IDT, OP, ACC, ITEMS>(a, si, t);
+        if (threadIdx.x >= 64) return;   // waves 1..3 are done; wave 0 publishes and combines
         if (a.mode == DR_MODE_BATCH) combine_tile_batch<P>(a, tag, t, si, part);
         else combine_member<P>(a, tag, 0, 0, t, T, 0, part);
     } else if (t == 0 && threadIdx.x == 0) {   // no tiles at all
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(LaunchArgs a) {
 
 template <int IDT, int OP, int ACC, int ITEMS>
 hipError_t launch_reduce(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
-    hipError_t e = launch_epoch_bump(a.ws, stream);
+    hipError_t e = launch_prologue(a, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_reduce<IDT, OP, ACC, ITEMS>), dim3((uint32_t)grid), dim3(kBlock), 0,
                        stream, a);

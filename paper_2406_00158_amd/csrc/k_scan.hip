@@ -46,56 +46,102 @@ __device__ __forceinline__ T shfl_up1(T v) {
     return lane_id() == 0 ? (T)0 : u;
 }
 
-// Exclusive carry of the tile at processing index r: sum of the
+// Exclusive carry of the tile at processing index r: the sum of the
 // aggregates of tiles r-1, r-2, ... down to the nearest tile whose
 // inclusive prefix is published (which is then added), or down to `stop`.
-// Called by one whole wave.
+// The whole workgroup looks back at once: thread i examines predecessor
+// hi - i, so one round trip to memory covers 256 predecessors. Tiles start
+// so fast (hundreds per microsecond at full bandwidth) that the nearest
+// published inclusive prefix is often hundreds of tiles back; a 64-wide
+// window would need several round trips. Returns the carry in every thread.
 template <class C>
 __device__ __forceinline__ C look_back(const LaunchArgs& a, uint32_t tag, int64_t r, int64_t stop) {
+    constexpr int WAVES = kBlock / 64;
+    __shared__ uint64_t s_incl_m[WAVES], s_have_m[WAVES];
+    __shared__ C s_part[WAVES];
+    __shared__ int s_timeout;
     const uint64_t* tw = (const uint64_t*)(a.ws + a.lay.off_tile);
     const int64_t TW = a.lay.tile_words;
-    const int l = lane_id();
+    const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
     C acc = (C)0;
     int64_t hi = r - 1;
     Deadline dl(a.spin_ticks);
     while (true) {
-        const int64_t p = hi - l;
+        // 1. one thread waits, with growing back-off, until the nearest
+        //    unconsumed predecessor has published something: polling with
+        //    the whole workgroup would add memory traffic that queues
+        //    behind the stream the scan itself is moving
+        if (tid == 0) {
+            int t_out = 0;
+            if (hi >= stop) {
+                const uint64_t* wp = tw + hi * TW;
+                int nap = 1;
+                while (true) {
+                    const uint64_t a1 = atomic_ld(wp + kAggWord + 1), i1 = atomic_ld(wp + kInclWord + 1);
+                    if ((uint32_t)(a1 >> 32) == tag || (uint32_t)(i1 >> 32) == tag) break;
+                    if (dl.passed()) {
+                        t_out = 1;
+                        break;
+                    }
+                    for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(2);
+                    nap = nap < 16 ? 2 * nap : 16;
+                }
+            }
+            s_timeout = t_out;
+        }
+        __syncthreads();
+        if (s_timeout) {
+            if (tid == 0) flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
+            break;
+        }
+        // 2. one read of the statuses of up to 256 predecessors
+        const int64_t p = hi - tid;
         const bool inr = p >= stop;
         uint64_t ib = 0, ab = 0;
         bool iok = false, aok = false;
         if (inr) {
-            const uint64_t* w = tw + p * TW;
-            const uint64_t a0 = atomic_ld(w + kAggWord), a1 = atomic_ld(w + kAggWord + 1);
-            const uint64_t i0 = atomic_ld(w + kInclWord), i1 = atomic_ld(w + kInclWord + 1);
+            const uint64_t* wp = tw + p * TW;
+            const uint64_t a0 = atomic_ld(wp + kAggWord), a1 = atomic_ld(wp + kAggWord + 1);
+            const uint64_t i0 = atomic_ld(wp + kInclWord), i1 = atomic_ld(wp + kInclWord + 1);
             iok = (uint32_t)(i0 >> 32) == tag && (uint32_t)(i1 >> 32) == tag;
             aok = (uint32_t)(a0 >> 32) == tag && (uint32_t)(a1 >> 32) == tag;
             ib = (uint64_t)(uint32_t)i0 | ((uint64_t)(uint32_t)i1 << 32);
             ab = (uint64_t)(uint32_t)a0 | ((uint64_t)(uint32_t)a1 << 32);
         }
-        const uint64_t incl_m = __ballot(!inr || iok);
-        const uint64_t have_m = __ballot(!inr || iok || aok);
-        const int f = incl_m ? __builtin_ctzll(incl_m) : 64;     // nearest inclusive or range start
-        const int z = (~have_m) ? __builtin_ctzll(~have_m) : 64; // nearest lane with nothing yet
+        const uint64_t im = __ballot(!inr || iok);
+        const uint64_t hm = __ballot(!inr || iok || aok);
+        if (l == 0) {
+            s_incl_m[w] = im;
+            s_have_m[w] = hm;
+        }
+        __syncthreads();
+        // f: first thread whose predecessor has an inclusive prefix (or lies
+        // before the range start); z: first thread whose predecessor has
+        // published nothing. The same in every thread.
+        int f = kBlock, z = kBlock;
+        for (int i = WAVES - 1; i >= 0; --i) {
+            if (s_incl_m[i]) f = 64 * i + __builtin_ctzll(s_incl_m[i]);
+            if (~s_have_m[i]) z = 64 * i + __builtin_ctzll(~s_have_m[i]);
+        }
+        C v = (C)0;
+        int consumed;
+        bool done = false;
         if (f <= z) {
-            C v = (C)0;
-            if (l < f) v = from_bits<C>(ab);
-            else if (l == f && inr) v = from_bits<C>(ib);
-            acc += wave_sum(v);
-            if (f < 64) break;
-            hi -= 64;
-            continue;
+            if (tid < f) v = from_bits<C>(ab);
+            else if (tid == f && inr) v = from_bits<C>(ib);
+            consumed = kBlock;
+            done = f < kBlock;
+        } else {
+            if (tid < z) v = from_bits<C>(ab);
+            consumed = z;
         }
-        if (z > 0) {   // consume the ready aggregates nearest to r
-            C v = l < z ? from_bits<C>(ab) : (C)0;
-            acc += wave_sum(v);
-            hi -= z;
-            continue;
-        }
-        if (dl.passed()) {
-            if (l == 0) flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+        const C wsum = wave_sum(v);
+        if (l == 0) s_part[w] = wsum;
+        __syncthreads();
+        for (int i = 0; i < WAVES; ++i) acc += s_part[i];
+        __syncthreads();   // masks and partial sums are rewritten next round
+        if (done) break;
+        hi -= consumed;
     }
     return acc;
 }
@@ -140,7 +186,6 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
     using C = carry_t<IDT, C64>;
     using O = typename elem<ODT>::T;
     __shared__ L s_wtot[WAVES];
-    __shared__ C s_excl;
     __shared__ double s_red[WAVES];
 
     const int64_t stop = a.mode == DR_MODE_BATCH ? (rev ? T - (si.first + si.ntiles) : si.first) : 0;
@@ -210,27 +255,21 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
 
     L woff = (L)0;
     for (int i = 0; i < w; ++i) woff += s_wtot[i];
-    if (w == 0) {
-        L tl = (L)0;
-        for (int i = 0; i < WAVES; ++i) tl += s_wtot[i];
-        const C agg = (C)tl;
-        C excl = (C)0;
-        uint64_t* tw = (uint64_t*)(a.ws + a.lay.off_tile) + r * (int64_t)a.lay.tile_words;
-        if (r != stop) {
-            if (l == 0) tagged_store(tw + kAggWord, tag, to_bits(agg));
-            excl = look_back<C>(a, tag, r, stop);
-        }
-        if (l == 0) {
-            tagged_store(tw + kInclWord, tag, to_bits(excl + agg));
-            s_excl = excl;
-        }
+    L tl = (L)0;
+    for (int i = 0; i < WAVES; ++i) tl += s_wtot[i];
+    const C agg = (C)tl;
+    C excl = (C)0;
+    uint64_t* tw = (uint64_t*)(a.ws + a.lay.off_tile) + r * (int64_t)a.lay.tile_words;
+    if (r != stop) {
+        if (threadIdx.x == 0) tagged_store(tw + kAggWord, tag, to_bits(agg));
+        excl = look_back<C>(a, tag, r, stop);
     }
+    if (threadIdx.x == 0) tagged_store(tw + kInclWord, tag, to_bits(excl + agg));
     if constexpr (FUSED) {
         const double wr = wave_sum(rpart_thread);
         if (l == 0) s_red[w] = wr;
+        __syncthreads();
     }
-    __syncthreads();
-    const C excl = s_excl;
 
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -245,7 +284,6 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
         if (threadIdx.x == 0)
             for (int i = 0; i < WAVES; ++i) part += s_red[i];
     }
-    __syncthreads();   // shared scratch is reused by the next tile
     return part;
 }
 
@@ -278,6 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(LaunchArgs a) {
         }
         const double part = scan_tile<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS>(a, tag, r, t, T, si, rev);
         if constexpr (FUSED) {
+            if (threadIdx.x >= 64) return;   // wave 0 publishes the partial and combines
             if (a.mode == DR_MODE_BATCH) combine_tile_batch<double>(a, tag, t, si, part);
             else combine_member<double>(a, tag, 0, 0, t, T, 0, part);
         }
@@ -289,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(LaunchArgs a) {
 
 template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS>
 hipError_t launch_scan(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
-    hipError_t e = launch_epoch_bump(a.ws, stream);
+    hipError_t e = launch_prologue(a, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_scan<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS>), dim3((uint32_t)grid),
                        dim3(kBlock), 0, stream, a);
@@ -310,23 +349,35 @@ hipError_t launch_scan(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
 LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items) {
     if (in_dt == DR_I32 || in_dt == DR_F64) carry64 = true;
     DR_SCAN_OPS(DR_I32, DR_I64, true, 16)
+    DR_SCAN_OPS(DR_I32, DR_I64, true, 32)
+    DR_SCAN_OPS(DR_I32, DR_I64, true, 64)
     DR_SCAN_OPS(DR_I32, DR_I32, true, 16)
     DR_SCAN_OPS(DR_F32, DR_F32, true, 16)
+    DR_SCAN_OPS(DR_F32, DR_F32, true, 32)
+    DR_SCAN_OPS(DR_F32, DR_F32, true, 64)
     DR_SCAN_OPS(DR_F32, DR_F32, false, 16)
     DR_SCAN_OPS(DR_BF16, DR_F32, true, 16)
     DR_SCAN_OPS(DR_F64, DR_F64, true, 16)
     return nullptr;
 }
 
+#define DR_FUSED(ITEMS)                                                                                  \
+    if (items == ITEMS) {                                                                                \
+        if (acc == DR_ACC_COMPENSATED)                                                                   \
+            return launch_scan<DR_F32, DR_F32, DR_OP_IDENTITY, true, true, DR_OP_MUL, DR_ACC_COMPENSATED, \
+                               ITEMS>;                                                                   \
+        return launch_scan<DR_F32, DR_F32, DR_OP_IDENTITY, true, true, DR_OP_MUL, DR_ACC_PLAIN, ITEMS>;   \
+    }
+
 LaunchFn find_scan_reduce(int in_dt, int reduce_op, int acc, int items) {
-    if (items != 16) return nullptr;
-    if (in_dt == DR_F64 && reduce_op == DR_OP_MUL)
-        return launch_scan<DR_F64, DR_F64, DR_OP_IDENTITY, true, true, DR_OP_MUL, DR_ACC_PLAIN, 16>;
+    if (reduce_op != DR_OP_MUL) return nullptr;
+    if (in_dt == DR_F64)
+        return items == 16 ? launch_scan<DR_F64, DR_F64, DR_OP_IDENTITY, true, true, DR_OP_MUL, DR_ACC_PLAIN, 16>
+                           : nullptr;
     if (in_dt != DR_F32) return nullptr;
-    if (reduce_op == DR_OP_MUL && acc == DR_ACC_COMPENSATED)
-        return launch_scan<DR_F32, DR_F32, DR_OP_IDENTITY, true, true, DR_OP_MUL, DR_ACC_COMPENSATED, 16>;
-    if (reduce_op == DR_OP_MUL && acc == DR_ACC_PLAIN)
-        return launch_scan<DR_F32, DR_F32, DR_OP_IDENTITY, true, true, DR_OP_MUL, DR_ACC_PLAIN, 16>;
+    DR_FUSED(16)
+    DR_FUSED(32)
+    DR_FUSED(64)
     return nullptr;
 }
 
