@@ -105,6 +105,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="run only a plain copy (for_each identity, 2^28 f32) K times: the known-size "
+                         "kernel that calibrates the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -132,6 +135,15 @@ def main() -> int:
     def seg(t):
         k = N // SEGMENTS
         return [t[i * k:(i + 1) * k] for i in range(SEGMENTS)]
+
+    if args.copy_only:
+        t_copy = B.segments([seg(b)], [seg(a)])
+        v_copy = B.make_view("identity", B.DR_F32)
+        for _ in range(args.warmup + args.steps):
+            B.dr_for_each(t_copy, v_copy, B.DR_F32, host_check=False)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 8 * N, "launches": args.warmup + args.steps}), flush=True)
+        return 0
 
     t_triad = B.segments([seg(b), seg(c)], [seg(a)])
     t_dot = B.segments([seg(b), seg(c)])

@@ -168,13 +168,19 @@ typedef struct dr_table {
 
 /* Launch shape. block_threads: 256 (the only shape built in this version);
  * items_per_thread: elements per thread per tile, one of the values
- * dr_tuning_supported accepts. NULL = the built-in default for the call. */
+ * dr_tuning_supported accepts; flags: DR_TUNE_* bits. NULL = the built-in
+ * default for the call. */
 typedef struct dr_tuning {
     int32_t block_threads;
     int32_t items_per_thread;
-    int32_t reserved0;
-    int32_t reserved1;
+    int32_t flags;
+    int32_t reserved;   /* must be 0 */
 } dr_tuning;
+
+/* dr_tuning.flags: CONCAT transform_reduce with one workgroup per tile and
+ * a per-tile combine, instead of the default streaming grid of resident
+ * workgroups (each summing many tiles, one combine per workgroup). */
+enum { DR_TUNE_TILE_PER_BLOCK = 1 };
 
 /* Library version (DR_ABI_VERSION). Never fails. */
 int dr_abi_version(void);

@@ -58,7 +58,7 @@ class dr_table(ctypes.Structure):
 
 class dr_tuning(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("items_per_thread", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(dr_segment) == 64
@@ -125,10 +125,13 @@ def make_view(op: int | str, in_dtype: int | torch.dtype, alpha: float = 0.0) ->
     return dr_view(OP_ARITY[op], dt, op, 0, float(alpha))
 
 
-def make_tuning(items_per_thread: int | None) -> dr_tuning | None:
-    if items_per_thread is None:
+DR_TUNE_TILE_PER_BLOCK = 1
+
+
+def make_tuning(items_per_thread: int | None, flags: int = 0) -> dr_tuning | None:
+    if items_per_thread is None and not flags:
         return None
-    return dr_tuning(256, int(items_per_thread), 0, 0)
+    return dr_tuning(256, int(items_per_thread or 0), int(flags), 0)
 
 
 # --- segment tables -----------------------------------------------------------

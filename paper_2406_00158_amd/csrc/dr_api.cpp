@@ -172,7 +172,7 @@ dr_status check_host_rows(const dr_table* t, int arity, int nout, int ies, int o
 dr_status resolve_items(const dr_tuning* tu, int algo, int in_dt, int& items) {
     items = default_items(algo, in_dt);
     if (!tu) return DR_OK;
-    if (tu->reserved0 || tu->reserved1) return fail(DR_ERR_INVALID_ARG, "tuning.reserved must be 0");
+    if ((tu->flags & ~DR_TUNE_TILE_PER_BLOCK) || tu->reserved) return fail(DR_ERR_INVALID_ARG, "unknown tuning bits");
     if (tu->block_threads != 0 && tu->block_threads != kBlock)
         return fail(DR_ERR_UNSUPPORTED, "block_threads must be %d", kBlock);
     if (tu->items_per_thread != 0) items = tu->items_per_thread;
@@ -261,6 +261,18 @@ dr_status prepare(const dr_table* t, int algo, int in_dt, int out_dt, int arity,
     p.grid = tmax;
     return DR_OK;
 }
+
+}  // namespace
+
+int dr::resident_grid(const void* kernel) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess) per = 1;
+    return std::max(cus, 1) * std::max(per, 1);
+}
+
+namespace {
 
 dr_status launch(LaunchFn fn, const Prepared& p, void* stream, const char* what) {
     hipError_t e = fn(p.a, p.grid, (hipStream_t)stream);
@@ -385,6 +397,7 @@ dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "reduce kernel not built for items_per_thread %d", items);
     p.a.alpha = view->alpha;
     p.a.result = result;
+    if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) p.a.flags |= kFlagTilePerBlock;
     if (view->in_dtype == DR_I32) p.a.init_i = *(const int64_t*)init;
     else p.a.init_f = *(const double*)init;
     return launch(fn, p, stream, "transform_reduce launch");

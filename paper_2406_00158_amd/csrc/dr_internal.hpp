@@ -85,6 +85,13 @@ struct LaunchArgs {
 // tags are preceded by the epoch prologue).
 typedef hipError_t (*LaunchFn)(const LaunchArgs& a, int64_t grid, hipStream_t stream);
 
+// Internal launch flag (LaunchArgs.flags, above the public scan flags):
+// CONCAT reduce with one workgroup per tile instead of the streaming grid.
+constexpr uint32_t kFlagTilePerBlock = 1u << 16;
+
+// Workgroups of `kernel` (256 threads) that can be resident at once.
+int resident_grid(const void* kernel);
+
 // The prologue of every launch that uses tags: epoch + 1, and the launch's
 // arrival counters (if any) set to 0.
 hipError_t launch_prologue(const LaunchArgs& a, hipStream_t stream);

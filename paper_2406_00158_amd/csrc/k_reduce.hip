@@ -146,12 +146,141 @@ __global__ __launch_bounds__(kBlock) void k_reduce(LaunchArgs a) {
     }
 }
 
+// Per-thread sum of one tile's elements (already in registers), widened to
+// the partial type. COMPENSATED: binary32 (sum, error) pair over the tile,
+// then widened exactly; PLAIN: binary32 running sum, widened.
+template <int IDT, int OP, int ACC, int SLOTS>
+__device__ __forceinline__ partial_t<IDT> thread_tile_sum(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS],
+                                                         double alpha_d) {
+    constexpr int V = vwidth<IDT>();
+    constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
+    using P = partial_t<IDT>;
+    if constexpr ((IDT == DR_F32 || IDT == DR_BF16) && ACC == DR_ACC_COMPENSATED) {
+        const float alpha = (float)alpha_d;
+        float s = 0.0f, c = 0.0f;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const float x0 = decode<IDT>(x[q].e[e]);
+                float p, pe;
+                if constexpr (OP == DR_OP_IDENTITY) {
+                    p = x0;
+                    pe = 0.0f;
+                } else if constexpr (OP == DR_OP_SQUARE) {
+                    two_prod(x0, x0, p, pe);
+                } else if constexpr (OP == DR_OP_MUL) {
+                    two_prod(x0, decode<IDT>(y[q].e[e]), p, pe);
+                } else {
+                    float m, me, r;
+                    two_prod(alpha, decode<IDT>(y[q].e[e]), m, me);
+                    two_sum(x0, m, p, r);
+                    pe = r + me;
+                }
+                float err;
+                two_sum(s, p, s, err);
+                c += err + pe;
+            }
+        }
+        return __builtin_isfinite(s) ? (double)s + (double)c : (double)s;
+    } else if constexpr (IDT == DR_F32 || IDT == DR_BF16) {
+        const float alpha = (float)alpha_d;
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const float x1 = ZIP ? decode<IDT>(y[q].e[e]) : 0.0f;
+                acc += view_apply<OP, float>(decode<IDT>(x[q].e[e]), x1, alpha);
+            }
+        }
+        return (double)acc;
+    } else {
+        const P alpha = (P)alpha_d;
+        P acc = (P)0;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const P x1 = ZIP ? (P)decode<IDT>(y[q].e[e]) : (P)0;
+                acc += view_apply<OP, P>((P)decode<IDT>(x[q].e[e]), x1, alpha);
+            }
+        }
+        return acc;
+    }
+}
+
+// CONCAT streaming form: a grid of resident workgroups, workgroup b taking
+// tiles b, b + G, b + 2G, ... with the loads of its next tile in flight while
+// it sums the current one. Each thread keeps a binary64 (int64) sum over its
+// tiles; the workgroup publishes one partial and the partials of the G
+// workgroups are combined in workgroup order. The tile-to-workgroup map is
+// fixed for a given grid, so the result is the same from run to run.
+template <int IDT, int OP, int ACC, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_reduce_stream(LaunchArgs a) {
+    constexpr int V = vwidth<IDT>();
+    constexpr int SLOTS = ITEMS / V;
+    constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
+    constexpr int WAVES = kBlock / 64;
+    using P = partial_t<IDT>;
+    __shared__ P s_wave[WAVES];
+    const uint32_t tag = begin_launch(a.ws);
+    TileMap tm;
+    tm.init(a);
+    if (!tm.ok) return;
+    const int64_t T = tm.total_tiles;
+    const int64_t G = gridDim.x;
+    const int w = threadIdx.x >> 6, l = lane_id();
+    P mine = (P)0;
+    vec<IDT> xa[SLOTS], ya[SLOTS], xb[SLOTS], yb[SLOTS];
+    int64_t t = blockIdx.x;
+    SegInfo sa, sb;
+    bool ha = t < T && tm.find(a, t, sa);
+    if (ha) {
+        load_slots<IDT, SLOTS>(xa, sa.in0, sa, (t - sa.first) * a.tile, w, l, false);
+        if constexpr (ZIP) load_slots<IDT, SLOTS>(ya, sa.in1, sa, (t - sa.first) * a.tile, w, l, false);
+    }
+    while (ha) {
+        const int64_t tb = t + G;
+        const bool hb = tb < T && tm.find(a, tb, sb);
+        if (hb) {
+            load_slots<IDT, SLOTS>(xb, sb.in0, sb, (tb - sb.first) * a.tile, w, l, false);
+            if constexpr (ZIP) load_slots<IDT, SLOTS>(yb, sb.in1, sb, (tb - sb.first) * a.tile, w, l, false);
+        }
+        mine += thread_tile_sum<IDT, OP, ACC, SLOTS>(xa, ya, a.alpha);
+        if (!hb) break;
+        const int64_t ta = tb + G;
+        ha = ta < T && tm.find(a, ta, sa);
+        if (ha) {
+            load_slots<IDT, SLOTS>(xa, sa.in0, sa, (ta - sa.first) * a.tile, w, l, false);
+            if constexpr (ZIP) load_slots<IDT, SLOTS>(ya, sa.in1, sa, (ta - sa.first) * a.tile, w, l, false);
+        }
+        mine += thread_tile_sum<IDT, OP, ACC, SLOTS>(xb, yb, a.alpha);
+        t = ta;
+    }
+    const P wsum = wave_sum(mine);
+    if (l == 0) s_wave[w] = wsum;
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    P part = (P)0;
+    if (l == 0)
+        for (int i = 0; i < WAVES; ++i) part += s_wave[i];
+    combine_member<P>(a, tag, 0, 0, blockIdx.x, G, 0, part);
+}
+
 template <int IDT, int OP, int ACC, int ITEMS>
 hipError_t launch_reduce(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
     hipError_t e = launch_prologue(a, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_reduce<IDT, OP, ACC, ITEMS>), dim3((uint32_t)grid), dim3(kBlock), 0,
-                       stream, a);
+    if (a.mode == DR_MODE_CONCAT && (a.flags & kFlagTilePerBlock) == 0) {
+        static const int resident = resident_grid((const void*)k_reduce_stream<IDT, OP, ACC, ITEMS>);
+        if (grid > resident) grid = resident;
+        hipLaunchKernelGGL((k_reduce_stream<IDT, OP, ACC, ITEMS>), dim3((uint32_t)grid), dim3(kBlock), 0,
+                           stream, a);
+    } else {
+        hipLaunchKernelGGL((k_reduce<IDT, OP, ACC, ITEMS>), dim3((uint32_t)grid), dim3(kBlock), 0,
+                           stream, a);
+    }
     return hipGetLastError();
 }
 
@@ -171,12 +300,16 @@ LaunchFn find_reduce(int in_dt, int op, int acc, int items) {
     if (in_dt == DR_I32 || in_dt == DR_F64) acc = DR_ACC_PLAIN;
     DR_RED_OPS(DR_F32, DR_ACC_COMPENSATED, 16)
     DR_RED_OPS(DR_F32, DR_ACC_COMPENSATED, 32)
+    DR_RED_OPS(DR_F32, DR_ACC_COMPENSATED, 64)
     DR_RED_OPS(DR_F32, DR_ACC_PLAIN, 16)
     DR_RED_OPS(DR_F32, DR_ACC_PLAIN, 32)
+    DR_RED_OPS(DR_F32, DR_ACC_PLAIN, 64)
     DR_RED_OPS(DR_BF16, DR_ACC_COMPENSATED, 16)
     DR_RED_OPS(DR_BF16, DR_ACC_COMPENSATED, 32)
+    DR_RED_OPS(DR_BF16, DR_ACC_COMPENSATED, 64)
     DR_RED_OPS(DR_BF16, DR_ACC_PLAIN, 16)
     DR_RED_OPS(DR_BF16, DR_ACC_PLAIN, 32)
+    DR_RED_OPS(DR_BF16, DR_ACC_PLAIN, 64)
     DR_RED_OPS(DR_I32, DR_ACC_PLAIN, 16)
     DR_RED_OPS(DR_F64, DR_ACC_PLAIN, 16)
     return nullptr;

@@ -130,6 +130,25 @@ def test_transform_reduce(seg_name, lengths, in_dt, op, mode, acc):
         assert abs(g - w) <= bound, (g, w, bound)
 
 
+@pytest.mark.parametrize("seg_name,lengths", SEGMENTATIONS)
+@pytest.mark.parametrize("in_dt", [B.DR_F32, B.DR_I32])
+def test_reduce_tile_per_block_form(seg_name, lengths, in_dt):
+    # the CONCAT reduce's alternative launch form (one workgroup per tile)
+    announce("reduce tile-per-block", seg_name, in_dt)
+    n = sum(lengths)
+    x, y = _values(in_dt, n, 13), _values(in_dt, n, 14)
+    tab, _ = _table([x, y], lengths, "carved", offsets=[0, 0])
+    is_int = in_dt == B.DR_I32
+    res = torch.zeros(1, dtype=torch.int64 if is_int else torch.float64, device=dev())
+    B.dr_transform_reduce(tab, B.make_view("mul", in_dt), B.DR_ACC_COMPENSATED, 0, res,
+                          tuning=B.make_tuning(16, B.DR_TUNE_TILE_PER_BLOCK))
+    want, mag = O.reduce(I.split(x, lengths), I.split(y, lengths), OR_DT[in_dt], O.MUL)
+    if is_int:
+        assert res.item() == int(want[0])
+    else:
+        assert abs(res.item() - want[0]) <= reduce_bound(mag[0], "compensated", tiles=n // 4096 + 200)
+
+
 def test_reduce_is_deterministic_and_reusable():
     announce("reduce determinism")
     lengths = I.lengths_dirichlet(3_000_000, 16, 1.0, 5)
