@@ -433,14 +433,37 @@ template <int DT> __device__ __forceinline__ typename elem<DT>::T zero_elem() {
     return (typename elem<DT>::T)0;
 }
 
+// True when the whole tile lies inside its segment and every pointer of the
+// row is 16-byte aligned there: all accesses are whole 16-byte vectors with
+// no bounds checks (the common case; only a segment's first and last tiles,
+// and misaligned rows, take the checked path).
+template <int V, int SLOTS>
+__device__ __forceinline__ bool tile_full(const SegInfo& si, int64_t u0) {
+    constexpr int64_t TILE = (int64_t)kBlock * SLOTS * V;
+    const int64_t j0 = u0 - si.shift;
+    return si.vec_ok && j0 >= 0 && j0 + TILE <= si.n;
+}
+
 template <int DT, int SLOTS>
 __device__ __forceinline__ void load_slots(vec<DT> (&x)[SLOTS], const void* base, const SegInfo& si,
                                            int64_t u0, int w, int l, bool rev) {
     constexpr int V = vwidth<DT>();
     constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+    const int64_t p0 = (int64_t)(w * SLOTS) * 64 + l;
+    if (tile_full<V, SLOTS>(si, u0)) {
+        const int64_t q0 = rev ? (NV - 1 - p0) : p0;
+        const char* b = (const char*)base + (u0 - si.shift + q0 * V) * esize<DT>();
+        const int64_t step = rev ? -64 * 16 : 64 * 16;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            u32x4 wv = __builtin_nontemporal_load((const u32x4*)(b + s * step));
+            __builtin_memcpy(&x[s], &wv, 16);
+        }
+        return;
+    }
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const int64_t p = (int64_t)(w * SLOTS + s) * 64 + l;
+        const int64_t p = p0 + (int64_t)s * 64;
         const int64_t q = rev ? (NV - 1 - p) : p;
         const int64_t j = u0 + q * V - si.shift;
         if (si.vec_ok && j >= 0 && j + V <= si.n) {
@@ -457,15 +480,16 @@ __device__ __forceinline__ void load_slots(vec<DT> (&x)[SLOTS], const void* base
     }
 }
 
-// Store the V outputs of slot s (given in memory order).
+// Store the V outputs of slot s (given in memory order). `full` is
+// tile_full() of the tile.
 template <class OT, int V, int SLOTS>
 __device__ __forceinline__ void store_slot(void* base, const SegInfo& si, int64_t u0, int w, int l,
-                                           int s, bool rev, const OT (&o)[V]) {
+                                           int s, bool rev, bool full, const OT (&o)[V]) {
     constexpr int64_t NV = (int64_t)kBlock * SLOTS;
     const int64_t p = (int64_t)(w * SLOTS + s) * 64 + l;
     const int64_t q = rev ? (NV - 1 - p) : p;
     const int64_t j = u0 + q * V - si.shift;
-    if (si.vec_ok && j >= 0 && j + V <= si.n) {
+    if (full || (si.vec_ok && j >= 0 && j + V <= si.n)) {
         store_run<OT, V>(base, j, o);
     } else {
 #pragma unroll

@@ -93,6 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_for_each(LaunchArgs a) {
     const int64_t u0 = (t - si.first) * a.tile;
     const auto alpha = alpha_of<IDT, ODT>(a.alpha);
 
+    const bool full = tile_full<V, SLOTS>(si, u0);
     vec<IDT> x[SLOTS], y[SLOTS];
     load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, false);
     if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, false);
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_for_each(LaunchArgs a) {
             typename elem<IDT>::T yv = ZIP ? y[s].e[e] : zero_elem<IDT>();
             o[e] = Op::apply(x[s].e[e], yv, alpha);
         }
-        store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, false, o);
+        store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, false, full, o);
     }
 }
 
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_broadcast_mul(LaunchArgs a) {
     const int w = threadIdx.x >> 6, l = lane_id();
     const int64_t u0 = (t - si.first) * a.tile;
     const double g = a.g[a.mode == DR_MODE_BATCH ? si.k : 0];
+    const bool full = tile_full<V, SLOTS>(si, u0);
 
     vec<IDT> x[SLOTS], y[SLOTS];
     if constexpr (OP != DR_OP_IDENTITY) load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, false);
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_broadcast_mul(LaunchArgs a) {
                 typename elem<IDT>::T yv = ZIP ? y[s].e[e] : zero_elem<IDT>();
                 o[e] = (O)(g * dview<IDT, OP>(xv, yv, which, a.alpha));
             }
-            store_slot<O, V, SLOTS>(out, si, u0, w, l, s, false, o);
+            store_slot<O, V, SLOTS>(out, si, u0, w, l, s, false, full, o);
         }
     }
 }

@@ -174,9 +174,10 @@ __device__ __forceinline__ typename elem<ODT>::T scan_out(carry_t<IDT, C64> carr
 // One tile at processing index r (physical tile t). Whole workgroup.
 // FUSED: also returns (thread 0) the tile's sum of ROP over (in0, in1)
 // with accumulation RACC.
-template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS>
+template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
 __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, int64_t r, int64_t t, int64_t T,
-                                            const SegInfo& si, bool rev) {
+                                            const SegInfo& si) {
+    constexpr bool rev = REV;
     constexpr int V = vwidth<IDT>();
     constexpr int SLOTS = ITEMS / V;
     constexpr int WAVES = kBlock / 64;
@@ -193,32 +194,13 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
     const int64_t u0 = (t - si.first) * a.tile;
     const L alpha = (L)a.alpha;
 
+    const bool full = tile_full<V, SLOTS>(si, u0);
     vec<IDT> x[SLOTS], y[SLOTS];
     load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, rev);
     if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, rev);
 
-    // tile-local prefix, processing order
-    L pre[SLOTS][V];
-    L run = (L)0;
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        L v[V];
-#pragma unroll
-        for (int e = 0; e < V; ++e)
-            v[e] = scan_value<IDT, OP, L>(x[s].e[e], ZIP ? y[s].e[e] : zero_elem<IDT>(), alpha);
-        mirror_if(v, rev);
-        pre[s][0] = v[0];
-#pragma unroll
-        for (int e = 1; e < V; ++e) pre[s][e] = pre[s][e - 1] + v[e];
-        const L inc = wave_incl_scan(pre[s][V - 1]);
-        const L base = run + shfl_up1(inc);
-#pragma unroll
-        for (int e = 0; e < V; ++e) pre[s][e] = base + pre[s][e];
-        run = run + readlane(inc, 63);
-    }
-    if (l == 0) s_wtot[w] = run;
-
-    // fused reduction of the second view (not order-sensitive)
+    // fused reduction of the second view (not order-sensitive), before the
+    // scan values replace the loaded ones
     double rpart_thread = 0.0;
     if constexpr (FUSED && IDT == DR_F64) {
         double rs = 0.0;
@@ -251,6 +233,27 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
         }
         rpart_thread = (double)rs + (double)rc;
     }
+
+    // scan values in processing order; per slot, only the offset of the
+    // slot's first element is kept: the serial prefix inside the slot is
+    // recomputed (in the same order) when the outputs are formed
+    L v[SLOTS][V];
+    L base[SLOTS];
+    L run = (L)0;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            v[s][e] = scan_value<IDT, OP, L>(x[s].e[e], ZIP ? y[s].e[e] : zero_elem<IDT>(), alpha);
+        mirror_if(v[s], rev);
+        L tot = v[s][0];
+#pragma unroll
+        for (int e = 1; e < V; ++e) tot = tot + v[s][e];
+        const L inc = wave_incl_scan(tot);
+        base[s] = run + shfl_up1(inc);
+        run = run + readlane(inc, 63);
+    }
+    if (l == 0) s_wtot[w] = run;
     __syncthreads();
 
     L woff = (L)0;
@@ -274,10 +277,15 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         O o[V];
+        L pre = v[s][0];
+        o[0] = scan_out<IDT, ODT, C64>(excl, woff, base[s] + pre);
 #pragma unroll
-        for (int e = 0; e < V; ++e) o[e] = scan_out<IDT, ODT, C64>(excl, woff, pre[s][e]);
+        for (int e = 1; e < V; ++e) {
+            pre = pre + v[s][e];
+            o[e] = scan_out<IDT, ODT, C64>(excl, woff, base[s] + pre);
+        }
         mirror_if(o, rev);
-        store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, rev, o);
+        store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, rev, full, o);
     }
     double part = 0.0;
     if constexpr (FUSED) {
@@ -293,17 +301,16 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
 // increasing index order, so the lowest unfinished tile is always running
 // or next to start on its XCD: every wait ends (and each is also bounded by
 // a.spin_ticks, which turns a stuck wait into a device fault flag).
-template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS>
+template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
 __global__ __launch_bounds__(kBlock) void k_scan(LaunchArgs a) {
     const uint32_t tag = begin_launch(a.ws);
     TileMap tm;
     tm.init(a);
     if (!tm.ok) return;
     const int64_t T = tm.total_tiles;
-    const bool rev = (a.flags & DR_SCAN_REVERSE) != 0;
     const int64_t r = blockIdx.x;
     if (r < T) {
-        const int64_t t = rev ? T - 1 - r : r;
+        const int64_t t = REV ? T - 1 - r : r;
         SegInfo si;
         if (!tm.find(a, t, si)) {
             // malformed row (flagged): publish an inclusive 0 so that later
@@ -314,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(LaunchArgs a) {
             }
             return;
         }
-        const double part = scan_tile<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS>(a, tag, r, t, T, si, rev);
+        const double part = scan_tile<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, REV>(a, tag, r, t, T, si);
         if constexpr (FUSED) {
             if (threadIdx.x >= 64) return;   // wave 0 publishes the partial and combines
             if (a.mode == DR_MODE_BATCH) combine_tile_batch<double>(a, tag, t, si, part);
@@ -330,8 +337,12 @@ template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int
 hipError_t launch_scan(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
     hipError_t e = launch_prologue(a, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scan<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS>), dim3((uint32_t)grid),
-                       dim3(kBlock), 0, stream, a);
+    if (a.flags & DR_SCAN_REVERSE)
+        hipLaunchKernelGGL((k_scan<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, true>), dim3((uint32_t)grid),
+                           dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_scan<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, false>), dim3((uint32_t)grid),
+                           dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -346,18 +357,27 @@ hipError_t launch_scan(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
         }                                                                                           \
     }
 
+#define DR_SCAN_ID(IDT, ODT, C64, ITEMS)                                                           \
+    if (in_dt == IDT && out_dt == ODT && carry64 == C64 && items == ITEMS && op == DR_OP_IDENTITY) \
+        return launch_scan<IDT, ODT, DR_OP_IDENTITY, C64, false, 0, 0, ITEMS>;
+
+// Every op at 16 items per thread; the identity (plain scan) also at larger
+// tiles, the shapes the tuner chooses from.
 LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items) {
     if (in_dt == DR_I32 || in_dt == DR_F64) carry64 = true;
     DR_SCAN_OPS(DR_I32, DR_I64, true, 16)
-    DR_SCAN_OPS(DR_I32, DR_I64, true, 32)
-    DR_SCAN_OPS(DR_I32, DR_I64, true, 64)
+    DR_SCAN_ID(DR_I32, DR_I64, true, 32)
+    DR_SCAN_ID(DR_I32, DR_I64, true, 64)
     DR_SCAN_OPS(DR_I32, DR_I32, true, 16)
+    DR_SCAN_ID(DR_I32, DR_I32, true, 64)
     DR_SCAN_OPS(DR_F32, DR_F32, true, 16)
-    DR_SCAN_OPS(DR_F32, DR_F32, true, 32)
-    DR_SCAN_OPS(DR_F32, DR_F32, true, 64)
+    DR_SCAN_ID(DR_F32, DR_F32, true, 32)
+    DR_SCAN_ID(DR_F32, DR_F32, true, 64)
     DR_SCAN_OPS(DR_F32, DR_F32, false, 16)
     DR_SCAN_OPS(DR_BF16, DR_F32, true, 16)
+    DR_SCAN_ID(DR_BF16, DR_F32, true, 64)
     DR_SCAN_OPS(DR_F64, DR_F64, true, 16)
+    DR_SCAN_ID(DR_F64, DR_F64, true, 32)
     return nullptr;
 }
 
