@@ -177,9 +177,13 @@ typedef struct dr_tuning {
     int32_t reserved;   /* must be 0 */
 } dr_tuning;
 
-/* dr_tuning.flags: CONCAT transform_reduce with one workgroup per tile and
- * a per-tile combine, instead of the default streaming grid of resident
- * workgroups (each summing many tiles, one combine per workgroup). */
+/* dr_tuning.flags: one workgroup per tile instead of the default streaming
+ * grid of resident workgroups. For a CONCAT transform_reduce: a per-tile
+ * combine instead of each workgroup summing many tiles and combining once.
+ * For inclusive_scan / scan_reduce: tiles in block-index order, each
+ * workgroup looking back with all its threads, instead of workgroups that
+ * take tiles from a counter and overlap each tile's look-back with the
+ * loads of their next tile. */
 enum { DR_TUNE_TILE_PER_BLOCK = 1 };
 
 /* Library version (DR_ABI_VERSION). Never fails. */

@@ -208,6 +208,8 @@ WsLayout layout_for(int algo, int64_t m, int64_t tmax) {
     L.nunits = nunits;
     L.off_ucnt = off;
     off += align256(nunits * 4);
+    L.off_chunk = off;
+    if (algo == DR_ALGO_SCAN || algo == DR_ALGO_SCAN_REDUCE) off += align256((uint64_t)(4 + 4 * kMaxChunks) * 8);
     L.bytes = off;
     return L;
 }
@@ -264,11 +266,11 @@ dr_status prepare(const dr_table* t, int algo, int in_dt, int out_dt, int arity,
 
 }  // namespace
 
-int dr::resident_grid(const void* kernel) {
+int dr::resident_grid(const void* kernel, int threads) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess) per = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess) per = 1;
     return std::max(cus, 1) * std::max(per, 1);
 }
 
@@ -425,6 +427,7 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
     p.a.alpha = view->alpha;
     p.a.flags = flags;
+    if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) p.a.flags |= kFlagTilePerBlock;
     return launch(fn, p, stream, "inclusive_scan launch");
 }
 
@@ -453,6 +456,7 @@ dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view, const 
     LaunchFn fn = find_scan_reduce(in, reduce_view->op, acc, items);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "fused scan kernel not built for this combination");
     p.a.flags = flags;
+    if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) p.a.flags |= kFlagTilePerBlock;
     p.a.result = result;
     p.a.init_f = *(const double*)init;
     return launch(fn, p, stream, "scan_reduce launch");

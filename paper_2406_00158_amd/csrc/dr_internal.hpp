@@ -19,13 +19,14 @@ enum : uint32_t {
 
 constexpr int kBlock = 256;            // threads per workgroup (4 waves)
 constexpr int kGroupTiles = 64;        // tiles per first-level combine group
+constexpr int kMaxChunks = 2048;        // workgroups of a scan's first (tile totals) pass
 
 // First 256 bytes of every workspace.
 struct Header {
     uint32_t error;      // DR_DEVFLAG_* bits, sticky until dr_device_status
     uint32_t epoch;      // launches on this workspace; bumped by each launch's prologue
     uint32_t plan_tag;   // tag of the launch that wrote the plan words
-    uint32_t pad0;
+    uint32_t ticket;     // next tile index handed out by the streaming scan; zeroed by the prologue
     uint64_t plan_rows;  // key of the plan built by dr_plan
     int64_t plan_m;
     int64_t plan_tile;
@@ -51,6 +52,7 @@ struct WsLayout {
     uint64_t off_gcnt;         // uint32 [ngroups]: arrivals per combine group (zeroed by the prologue)
     uint64_t off_gpart;        // [ngroups * 2]: tagged group partials
     uint64_t off_ucnt;         // uint32 [nunits]: arrived groups per result (zeroed by the prologue)
+    uint64_t off_chunk;        // scans: [4 + 4 * kMaxChunks] chunk records of the reduce-then-scan form
     uint64_t bytes;            // total size
     uint64_t ngroups;          // counters at off_gcnt
     uint64_t nunits;           // counters at off_ucnt
@@ -89,8 +91,8 @@ typedef hipError_t (*LaunchFn)(const LaunchArgs& a, int64_t grid, hipStream_t st
 // CONCAT reduce with one workgroup per tile instead of the streaming grid.
 constexpr uint32_t kFlagTilePerBlock = 1u << 16;
 
-// Workgroups of `kernel` (256 threads) that can be resident at once.
-int resident_grid(const void* kernel);
+// Workgroups of `kernel` (of `threads` threads) that can be resident at once.
+int resident_grid(const void* kernel, int threads = kBlock);
 
 // The prologue of every launch that uses tags: epoch + 1, and the launch's
 // arrival counters (if any) set to 0.

@@ -171,38 +171,13 @@ __device__ __forceinline__ typename elem<ODT>::T scan_out(carry_t<IDT, C64> carr
     }
 }
 
-// One tile at processing index r (physical tile t). Whole workgroup.
-// FUSED: also returns (thread 0) the tile's sum of ROP over (in0, in1)
-// with accumulation RACC.
-template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
-__device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, int64_t r, int64_t t, int64_t T,
-                                            const SegInfo& si) {
-    constexpr bool rev = REV;
+// Per-thread sum of ROP over the zipped (in0, in1) elements of a loaded
+// tile, accumulated as RACC (the fused reduction; order-insensitive, so it
+// is taken before the scan values replace the loaded ones).
+template <int IDT, int ROP, int RACC, int SLOTS>
+__device__ __forceinline__ double fused_partial(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS]) {
     constexpr int V = vwidth<IDT>();
-    constexpr int SLOTS = ITEMS / V;
-    constexpr int WAVES = kBlock / 64;
-    constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY) ||
-                         (FUSED && (ROP == DR_OP_MUL || ROP == DR_OP_AXPY));
-    using L = local_t<IDT>;
-    using C = carry_t<IDT, C64>;
-    using O = typename elem<ODT>::T;
-    __shared__ L s_wtot[WAVES];
-    __shared__ double s_red[WAVES];
-
-    const int64_t stop = a.mode == DR_MODE_BATCH ? (rev ? T - (si.first + si.ntiles) : si.first) : 0;
-    const int w = threadIdx.x >> 6, l = lane_id();
-    const int64_t u0 = (t - si.first) * a.tile;
-    const L alpha = (L)a.alpha;
-
-    const bool full = tile_full<V, SLOTS>(si, u0);
-    vec<IDT> x[SLOTS], y[SLOTS];
-    load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, rev);
-    if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, rev);
-
-    // fused reduction of the second view (not order-sensitive), before the
-    // scan values replace the loaded ones
-    double rpart_thread = 0.0;
-    if constexpr (FUSED && IDT == DR_F64) {
+    if constexpr (IDT == DR_F64) {
         double rs = 0.0;
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
@@ -210,8 +185,8 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
             for (int e = 0; e < V; ++e)
                 rs += view_apply<ROP, double>(decode<IDT>(x[s].e[e]), decode<IDT>(y[s].e[e]), 0.0);
         }
-        rpart_thread = rs;
-    } else if constexpr (FUSED) {
+        return rs;
+    } else {
         float rs = 0.0f, rc = 0.0f;
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
@@ -231,21 +206,27 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
                 }
             }
         }
-        rpart_thread = (double)rs + (double)rc;
+        return (double)rs + (double)rc;
     }
+}
 
-    // scan values in processing order; per slot, only the offset of the
-    // slot's first element is kept: the serial prefix inside the slot is
-    // recomputed (in the same order) when the outputs are formed
-    L v[SLOTS][V];
-    L base[SLOTS];
+// Scan values of a loaded tile in processing order. Per slot only the
+// offset of the slot's first element inside the wave is kept (base[s]);
+// the serial prefix inside the slot is recomputed, in the same order, when
+// the outputs are formed. Returns the wave's total (every lane).
+template <int IDT, int OP, bool ZIP, int SLOTS, bool REV>
+__device__ __forceinline__ local_t<IDT> tile_values(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS],
+                                                    local_t<IDT> alpha, local_t<IDT> (&v)[SLOTS][vwidth<IDT>()],
+                                                    local_t<IDT> (&base)[SLOTS]) {
+    constexpr int V = vwidth<IDT>();
+    using L = local_t<IDT>;
     L run = (L)0;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
 #pragma unroll
         for (int e = 0; e < V; ++e)
             v[s][e] = scan_value<IDT, OP, L>(x[s].e[e], ZIP ? y[s].e[e] : zero_elem<IDT>(), alpha);
-        mirror_if(v[s], rev);
+        mirror_if(v[s], REV);
         L tot = v[s][0];
 #pragma unroll
         for (int e = 1; e < V; ++e) tot = tot + v[s][e];
@@ -253,6 +234,75 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
         base[s] = run + shfl_up1(inc);
         run = run + readlane(inc, 63);
     }
+    return run;
+}
+
+// Outputs of a tile: carry + offset of the wave + prefix inside the wave.
+template <int IDT, int ODT, bool C64, int SLOTS, bool REV>
+__device__ __forceinline__ void tile_write(const local_t<IDT> (&v)[SLOTS][vwidth<IDT>()],
+                                           const local_t<IDT> (&base)[SLOTS], carry_t<IDT, C64> excl,
+                                           local_t<IDT> woff, const SegInfo& si, int64_t u0, int w, int l,
+                                           bool full) {
+    constexpr int V = vwidth<IDT>();
+    using L = local_t<IDT>;
+    using O = typename elem<ODT>::T;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        O o[V];
+        L pre = v[s][0];
+        o[0] = scan_out<IDT, ODT, C64>(excl, woff, base[s] + pre);
+#pragma unroll
+        for (int e = 1; e < V; ++e) {
+            pre = pre + v[s][e];
+            o[e] = scan_out<IDT, ODT, C64>(excl, woff, base[s] + pre);
+        }
+        mirror_if(o, REV);
+        store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, REV, full, o);
+    }
+}
+
+template <int IDT, int OP, bool FUSED, int ROP>
+constexpr bool zip_view() {
+    return (OP == DR_OP_MUL || OP == DR_OP_AXPY) || (FUSED && (ROP == DR_OP_MUL || ROP == DR_OP_AXPY));
+}
+
+// Processing index of a BATCH segment's first tile (the look-back of a
+// tile stops there); 0 in CONCAT mode.
+template <bool REV>
+__device__ __forceinline__ int64_t stop_of(const LaunchArgs& a, const SegInfo& si, int64_t T) {
+    if (a.mode != DR_MODE_BATCH) return 0;
+    return REV ? T - (si.first + si.ntiles) : si.first;
+}
+
+// One tile at processing index r (physical tile t). Whole workgroup.
+// FUSED: also returns (thread 0) the tile's sum of ROP over (in0, in1)
+// with accumulation RACC.
+template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
+__device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, int64_t r, int64_t t, int64_t T,
+                                            const SegInfo& si) {
+    constexpr int V = vwidth<IDT>();
+    constexpr int SLOTS = ITEMS / V;
+    constexpr int WAVES = kBlock / 64;
+    constexpr bool ZIP = zip_view<IDT, OP, FUSED, ROP>();
+    using L = local_t<IDT>;
+    using C = carry_t<IDT, C64>;
+    __shared__ L s_wtot[WAVES];
+    __shared__ double s_red[WAVES];
+
+    const int64_t stop = stop_of<REV>(a, si, T);
+    const int w = threadIdx.x >> 6, l = lane_id();
+    const int64_t u0 = (t - si.first) * a.tile;
+
+    const bool full = tile_full<V, SLOTS>(si, u0);
+    vec<IDT> x[SLOTS], y[SLOTS];
+    load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, REV);
+    if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, REV);
+    double rpart_thread = 0.0;
+    if constexpr (FUSED) rpart_thread = fused_partial<IDT, ROP, RACC, SLOTS>(x, y);
+
+    L v[SLOTS][V];
+    L base[SLOTS];
+    const L run = tile_values<IDT, OP, ZIP, SLOTS, REV>(x, y, (L)a.alpha, v, base);
     if (l == 0) s_wtot[w] = run;
     __syncthreads();
 
@@ -273,20 +323,7 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
         if (l == 0) s_red[w] = wr;
         __syncthreads();
     }
-
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        O o[V];
-        L pre = v[s][0];
-        o[0] = scan_out<IDT, ODT, C64>(excl, woff, base[s] + pre);
-#pragma unroll
-        for (int e = 1; e < V; ++e) {
-            pre = pre + v[s][e];
-            o[e] = scan_out<IDT, ODT, C64>(excl, woff, base[s] + pre);
-        }
-        mirror_if(o, rev);
-        store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, rev, full, o);
-    }
+    tile_write<IDT, ODT, C64, SLOTS, REV>(v, base, excl, woff, si, u0, w, l, full);
     double part = 0.0;
     if constexpr (FUSED) {
         if (threadIdx.x == 0)
@@ -333,17 +370,284 @@ __global__ __launch_bounds__(kBlock) void k_scan(LaunchArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Reduce-then-scan form (the default)
+// ---------------------------------------------------------------------------
+//
+// A decoupled look-back makes every tile wait for the slowest of the
+// predecessors still loading, and thousands of tiles are loading at once:
+// at full bandwidth those waits, not the memory, set the pace. This form
+// never waits on another workgroup:
+//
+//   pass 1  (k_scan_sums)   a resident grid; workgroup g streams the
+//           contiguous chunk [g*Q, (g+1)*Q) of processing indices, forms
+//           each tile's total exactly as the scan pass will, and writes each
+//           tile's carry relative to the chunk start (or to the segment
+//           start, BATCH) plus the chunk's (has-head, trailing sum) pair;
+//   pass 1b (k_scan_chunks) one workgroup: segmented exclusive scan of the
+//           chunk pairs, giving each chunk its incoming carry;
+//   pass 2  (k_scan_apply)  one workgroup per tile: local scan in registers
+//           plus the tile's carry, written once. The fused reduction's
+//           partials and their combine run here.
+//
+// The input is read twice (12 bytes per binary32 element instead of 8), in
+// two streaming passes. The carries are sums in a fixed order, so results
+// are identical from run to run (for a given chunk count).
+//
+// The paper's scan is also a local pass, a scan of partial totals and a
+// second pass over the data (section 4.3, Algorithm 4); here the first pass
+// only reads, so the data is written once.
+
+// Chunk area: [0] Q (tiles per chunk), [1] chunk count; chunk g at word
+// 4 + 4g: [0] has a segment head, [1] carry bits of the sum after the last
+// head (or of the whole chunk), [2] incoming carry bits (pass 1b).
+constexpr int kChunkHdr = 4;
+
+// Tile record (processing index r), words [0, 1] of the tile words:
+// carry bits relative to the chunk start or the last head, and whether a
+// head lies in [chunk start, r].
+constexpr int kRecCarry = 0;
+constexpr int kRecHead = 1;
+
+template <int IDT, int OP, bool C64, int ITEMS, bool REV>
+__global__ __launch_bounds__(kBlock) void k_scan_sums(LaunchArgs a) {
+    constexpr int V = vwidth<IDT>();
+    constexpr int SLOTS = ITEMS / V;
+    constexpr int WAVES = kBlock / 64;
+    constexpr bool ZIP = zip_view<IDT, OP, false, 0>();
+    using L = local_t<IDT>;
+    using C = carry_t<IDT, C64>;
+    __shared__ L s_wtot[2][WAVES];
+    TileMap tm;
+    tm.init(a);
+    if (!tm.ok) return;
+    const int64_t T = tm.total_tiles;
+    const int64_t G = gridDim.x;
+    const int64_t Q = (T + G - 1) / G;
+    const int64_t g = blockIdx.x;
+    uint64_t* cw = (uint64_t*)(a.ws + a.lay.off_chunk);
+    uint64_t* tws = (uint64_t*)(a.ws + a.lay.off_tile);
+    const int64_t TW = a.lay.tile_words;
+    if (g == 0 && threadIdx.x == 0) {
+        cw[0] = (uint64_t)Q;
+        cw[1] = (uint64_t)G;
+    }
+    const int64_t r0 = g * Q < T ? g * Q : T;
+    const int64_t r1 = r0 + Q < T ? r0 + Q : T;
+    const int w = threadIdx.x >> 6, l = lane_id();
+    const L alpha = (L)a.alpha;
+
+    C run = (C)0;    // thread 0: carry of the next tile relative to the chunk / head
+    bool seen = false;
+    vec<IDT> xa[SLOTS], ya[SLOTS], xb[SLOTS], yb[SLOTS];
+    SegInfo sa, sb;
+    int64_t r = r0;
+    bool ha = false, hb = false;
+    auto tile_of = [&](int64_t rr) { return REV ? T - 1 - rr : rr; };
+    auto issue = [&](int64_t rr, SegInfo& si, vec<IDT> (&x)[SLOTS], vec<IDT> (&y)[SLOTS]) -> bool {
+        const int64_t t = tile_of(rr);
+        if (!tm.find(a, t, si)) return false;
+        const int64_t u0 = (t - si.first) * a.tile;
+        load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, REV);
+        if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, REV);
+        return true;
+    };
+    // one tile whose data is in (x, y): tile total, then (thread 0) its
+    // record. A malformed row (flagged) counts as a head with total 0.
+    auto consume = [&](int64_t rr, int i, bool ok, const SegInfo& si, const vec<IDT> (&x)[SLOTS],
+                       const vec<IDT> (&y)[SLOTS]) {
+        if (ok) {
+            L v[SLOTS][V];
+            L base[SLOTS];
+            const L wt = tile_values<IDT, OP, ZIP, SLOTS, REV>(x, y, alpha, v, base);
+            if (l == 0) s_wtot[i & 1][w] = wt;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            L tl = (L)0;
+            if (ok)
+                for (int k = 0; k < WAVES; ++k) tl += s_wtot[i & 1][k];
+            const bool head = !ok || rr == stop_of<REV>(a, si, T);
+            if (head) {
+                run = (C)0;
+                seen = true;
+            }
+            uint64_t* rec = tws + rr * TW;
+            rec[kRecCarry] = to_bits(run);
+            rec[kRecHead] = seen ? 1u : 0u;
+            run = run + (C)tl;
+        }
+    };
+    if (r < r1) ha = issue(r, sa, xa, ya);
+    for (int i = 0; r < r1; i += 2) {
+        if (r + 1 < r1) hb = issue(r + 1, sb, xb, yb);
+        consume(r, i, ha, sa, xa, ya);
+        if (++r >= r1) break;
+        if (r + 1 < r1) ha = issue(r + 1, sa, xa, ya);
+        consume(r, i + 1, hb, sb, xb, yb);
+        ++r;
+    }
+    if (threadIdx.x == 0) {
+        uint64_t* c = cw + kChunkHdr + 4 * g;
+        c[0] = seen ? 1u : 0u;
+        c[1] = to_bits(run);
+    }
+}
+
+// Segmented exclusive scan of the chunk pairs (has-head, sum) by one
+// workgroup of kScanChunkThreads threads. The pair operator is
+// (f1, s1) then (f2, s2) = (f1 | f2, f2 ? s2 : s1 + s2).
+constexpr int kScanChunkThreads = 1024;
+
+template <class C>
+__global__ __launch_bounds__(kScanChunkThreads) void k_scan_chunks(LaunchArgs a) {
+    constexpr int N = kScanChunkThreads;
+    __shared__ C s_v[2][N];
+    __shared__ uint8_t s_f[2][N];
+    uint64_t* cw = (uint64_t*)(a.ws + a.lay.off_chunk);
+    const int64_t G = cw[1] < (uint64_t)kMaxChunks ? (int64_t)cw[1] : kMaxChunks;
+    const int tid = threadIdx.x;
+    const int64_t K = (G + N - 1) / N;   // chunks per thread (consecutive)
+    // serial inclusive pair of this thread's chunks
+    bool f = false;
+    C sv = (C)0;
+    for (int64_t j = 0; j < K; ++j) {
+        const int64_t c = tid * K + j;
+        if (c >= G) break;
+        const uint64_t* cr = cw + kChunkHdr + 4 * c;
+        const bool fc = cr[0] != 0;
+        const C vc = from_bits<C>(cr[1]);
+        sv = fc ? vc : sv + vc;
+        f = f || fc;
+    }
+    // inclusive scan of the thread pairs (Hillis-Steele, double-buffered)
+    int cur = 0;
+    s_v[0][tid] = sv;
+    s_f[0][tid] = f ? 1 : 0;
+    __syncthreads();
+    for (int d = 1; d < N; d <<= 1) {
+        C v = s_v[cur][tid];
+        uint8_t fl = s_f[cur][tid];
+        if (tid >= d && !fl) {
+            v = s_v[cur][tid - d] + v;
+            fl = s_f[cur][tid - d];
+        }
+        s_v[cur ^ 1][tid] = v;
+        s_f[cur ^ 1][tid] = fl;
+        cur ^= 1;
+        __syncthreads();
+    }
+    // exclusive carry into this thread's first chunk, then serially on
+    C cin = tid > 0 ? s_v[cur][tid - 1] : (C)0;
+    for (int64_t j = 0; j < K; ++j) {
+        const int64_t c = tid * K + j;
+        if (c >= G) break;
+        uint64_t* cr = cw + kChunkHdr + 4 * c;
+        cr[2] = to_bits(cin);
+        const C vc = from_bits<C>(cr[1]);
+        cin = cr[0] != 0 ? vc : cin + vc;
+    }
+}
+
+template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
+__global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
+    constexpr int V = vwidth<IDT>();
+    constexpr int SLOTS = ITEMS / V;
+    constexpr int WAVES = kBlock / 64;
+    constexpr bool ZIP = zip_view<IDT, OP, FUSED, ROP>();
+    using L = local_t<IDT>;
+    using C = carry_t<IDT, C64>;
+    __shared__ L s_wtot[WAVES];
+    __shared__ double s_red[WAVES];
+    const uint32_t tag = FUSED ? begin_launch(a.ws) : 0u;
+    TileMap tm;
+    tm.init(a);
+    if (!tm.ok) return;
+    const int64_t T = tm.total_tiles;
+    const int64_t r = blockIdx.x;
+    if (r >= T) {
+        if (FUSED && T == 0 && r == 0 && threadIdx.x == 0) {   // no tiles at all
+            if (a.mode == DR_MODE_BATCH) write_all_init<double>(a);
+            else write_result<double>(a, 0, 0.0);
+        }
+        return;
+    }
+    const int64_t t = REV ? T - 1 - r : r;
+    SegInfo si;
+    if (!tm.find(a, t, si)) return;   // malformed row (flagged)
+    const int w = threadIdx.x >> 6, l = lane_id();
+    // the tile's carry: its record plus (before the first head of the
+    // chunk) the chunk's incoming carry
+    const uint64_t* cw = (const uint64_t*)(a.ws + a.lay.off_chunk);
+    const uint64_t* rec = (const uint64_t*)(a.ws + a.lay.off_tile) + r * a.lay.tile_words;
+    const int64_t Q = (int64_t)cw[0];
+    const uint64_t rc = rec[kRecCarry], rh = rec[kRecHead];
+    const uint64_t ci = cw[kChunkHdr + 4 * (r / Q) + 2];
+
+    const int64_t u0 = (t - si.first) * a.tile;
+    const bool full = tile_full<V, SLOTS>(si, u0);
+    vec<IDT> x[SLOTS], y[SLOTS];
+    load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, REV);
+    if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, REV);
+    double rpart_thread = 0.0;
+    if constexpr (FUSED) rpart_thread = fused_partial<IDT, ROP, RACC, SLOTS>(x, y);
+    L v[SLOTS][V];
+    L base[SLOTS];
+    const L run = tile_values<IDT, OP, ZIP, SLOTS, REV>(x, y, (L)a.alpha, v, base);
+    if (l == 0) s_wtot[w] = run;
+    if constexpr (FUSED) {
+        const double wr = wave_sum(rpart_thread);
+        if (l == 0) s_red[w] = wr;
+    }
+    __syncthreads();
+    L woff = (L)0;
+    for (int i = 0; i < w; ++i) woff += s_wtot[i];
+    const C excl = rh ? from_bits<C>(rc) : from_bits<C>(rc) + from_bits<C>(ci);
+    tile_write<IDT, ODT, C64, SLOTS, REV>(v, base, excl, woff, si, u0, w, l, full);
+    if constexpr (FUSED) {
+        if (threadIdx.x >= 64) return;   // wave 0 publishes the partial and combines
+        double part = 0.0;
+        if (l == 0)
+            for (int i = 0; i < WAVES; ++i) part += s_red[i];
+        if (a.mode == DR_MODE_BATCH) combine_tile_batch<double>(a, tag, t, si, part);
+        else combine_member<double>(a, tag, 0, 0, t, T, 0, part);
+    }
+}
+
+template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
+hipError_t launch_scan_dir(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
+    if (a.flags & kFlagTilePerBlock) {
+        hipLaunchKernelGGL((k_scan<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, REV>), dim3((uint32_t)grid),
+                           dim3(kBlock), 0, stream, a);
+        return hipGetLastError();
+    }
+    using C = carry_t<IDT, C64>;
+    static const int resident = resident_grid((const void*)k_scan_sums<IDT, OP, C64, ITEMS, REV>);
+    int64_t g1 = resident < kMaxChunks ? resident : kMaxChunks;
+    if (g1 > grid) g1 = grid;
+    if (g1 < 1) g1 = 1;
+    hipLaunchKernelGGL((k_scan_sums<IDT, OP, C64, ITEMS, REV>), dim3((uint32_t)g1), dim3(kBlock), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_scan_chunks<C>), dim3(1), dim3(kScanChunkThreads), 0, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_scan_apply<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, REV>), dim3((uint32_t)grid),
+                       dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
 template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS>
 hipError_t launch_scan(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
-    hipError_t e = launch_prologue(a, stream);
-    if (e != hipSuccess) return e;
+    // the prologue (epoch tag, zeroed counters) serves the single-pass form
+    // and the fused reduction's combine
+    if (FUSED || (a.flags & kFlagTilePerBlock)) {
+        hipError_t e = launch_prologue(a, stream);
+        if (e != hipSuccess) return e;
+    }
     if (a.flags & DR_SCAN_REVERSE)
-        hipLaunchKernelGGL((k_scan<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, true>), dim3((uint32_t)grid),
-                           dim3(kBlock), 0, stream, a);
-    else
-        hipLaunchKernelGGL((k_scan<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, false>), dim3((uint32_t)grid),
-                           dim3(kBlock), 0, stream, a);
-    return hipGetLastError();
+        return launch_scan_dir<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, true>(a, grid, stream);
+    return launch_scan_dir<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, false>(a, grid, stream);
 }
 
 #define DR_SCAN_OPS(IDT, ODT, C64, ITEMS)                                                           \

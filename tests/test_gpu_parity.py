@@ -184,21 +184,32 @@ SCAN_CASES = [(B.DR_I32, B.DR_I64), (B.DR_I32, B.DR_I32), (B.DR_F32, B.DR_F32), 
               (B.DR_F64, B.DR_F64)]
 
 
+# the default reduce-then-scan passes, and the single-pass form (one
+# workgroup per tile in block-index order, decoupled look-back)
+SCAN_FORMS = ["two_pass", "look_back"]
+
+
+def _scan_tuning(form, items=16):
+    return B.make_tuning(items, B.DR_TUNE_TILE_PER_BLOCK) if form == "look_back" else None
+
+
 @pytest.mark.parametrize("seg_name,lengths", SEGMENTATIONS)
 @pytest.mark.parametrize("in_dt,out_dt", SCAN_CASES)
 @pytest.mark.parametrize("mode", ["concat", "batch"])
 @pytest.mark.parametrize("reverse", [False, True])
-def test_inclusive_scan(seg_name, lengths, in_dt, out_dt, mode, reverse):
+@pytest.mark.parametrize("form", SCAN_FORMS)
+def test_inclusive_scan(seg_name, lengths, in_dt, out_dt, mode, reverse, form):
     op = B.DR_OP_IDENTITY
     layout, offs = LAYOUTS[(len(lengths) + int(reverse)) % len(LAYOUTS)]
-    announce("scan", seg_name, in_dt, out_dt, mode, reverse, layout)
+    announce("scan", seg_name, in_dt, out_dt, mode, reverse, layout, form)
     n = sum(lengths)
     x = _values(in_dt, n, 21)
     if in_dt == B.DR_I32 and out_dt == B.DR_I32:
         x = x * 10_000_000                                  # the int32 output wraps
     outs = empty_like_segments(lengths, B.TORCH_DTYPE[out_dt], "separate")
     tab, _ = _table([x], lengths, layout, outs=[outs], mode=mode, offsets=(offs or [0])[:1])
-    B.dr_inclusive_scan(tab, B.make_view(op, in_dt), out_dt, B.DR_SCAN_REVERSE if reverse else 0)
+    B.dr_inclusive_scan(tab, B.make_view(op, in_dt), out_dt, B.DR_SCAN_REVERSE if reverse else 0,
+                        tuning=_scan_tuning(form))
     got = gather(outs)
     omode = O.BATCH if mode == "batch" else O.CONCAT
     if in_dt == B.DR_I32:
@@ -281,9 +292,10 @@ def test_scan_in_place_and_reuse():
 
 @pytest.mark.parametrize("mode", ["batch", "concat"])
 @pytest.mark.parametrize("reverse", [False, True])
-def test_scan_reduce_fused(mode, reverse):
+@pytest.mark.parametrize("form", SCAN_FORMS)
+def test_scan_reduce_fused(mode, reverse, form):
     lengths = I.lengths_loguniform(300, 1 << 14, 1 << 20, 9)
-    announce("scan_reduce", mode, reverse, len(lengths))
+    announce("scan_reduce", mode, reverse, len(lengths), form)
     n = sum(lengths)
     x, y = I.normal_f32(n, 51), I.normal_f32(n, 52)
     outs = empty_like_segments(lengths, torch.float32)
@@ -291,7 +303,8 @@ def test_scan_reduce_fused(mode, reverse):
     nres = len(lengths) if mode == "batch" else 1
     res = torch.zeros(nres, dtype=torch.float64, device=dev())
     B.dr_scan_reduce(tab, B.make_view("identity", B.DR_F32), B.make_view("mul", B.DR_F32),
-                     B.DR_ACC_COMPENSATED, 0.0, res, B.DR_SCAN_REVERSE if reverse else 0)
+                     B.DR_ACC_COMPENSATED, 0.0, res, B.DR_SCAN_REVERSE if reverse else 0,
+                     tuning=_scan_tuning(form))
     omode = O.BATCH if mode == "batch" else O.CONCAT
     ref, absp = O.scan(I.split(x, lengths), None, O.F32, O.IDENTITY, mode=omode, reverse=reverse, want_abs=True)
     ref, absp = np.concatenate(ref), np.concatenate(absp)
@@ -344,4 +357,32 @@ def test_device_flags_bad_table_without_host_mirror():
     tab.total_length = 100
     B.dr_inclusive_scan(tab, B.make_view("identity", B.DR_F32), B.DR_F32, workspace=ws)
     assert np.array_equal(dev_to_np(out), np.arange(1, 101, dtype=np.float32))
+    assert ws.device_status() == 0
+
+
+@pytest.mark.parametrize("form", SCAN_FORMS)
+def test_scan_malformed_row_of_planned_table_is_flagged(form):
+    """A non-empty row without an output pointer, in a table large enough to
+    be planned on the device (the plan checks inputs only): the scan skips
+    that row's tiles (a zero carry restarts after them), flags the table,
+    and the launch completes."""
+    announce("malformed row", form)
+    lengths = [100] * 130
+    x = torch.ones(sum(lengths), device=dev())
+    out = torch.zeros(sum(lengths), device=dev())
+    ins = [x[100 * k:100 * (k + 1)] for k in range(130)]
+    outs = [out[100 * k:100 * (k + 1)] for k in range(130)]
+    tab = B.segments([ins], [outs])
+    tab.host_rows[50].out[0] = None
+    raw = np.frombuffer(bytes(tab.host_rows), dtype=np.uint8)[: 64 * 130]
+    tab.dev_rows = torch.from_numpy(raw.copy()).to(dev())
+    ws = B.Workspace(dev())
+    B.dr_inclusive_scan(tab, B.make_view("identity", B.DR_F32), B.DR_F32, workspace=ws, host_check=False,
+                        tuning=_scan_tuning(form))
+    torch.cuda.synchronize()
+    assert ws.device_status() & 1
+    good = B.segments([ins], [outs])
+    B.dr_inclusive_scan(good, B.make_view("identity", B.DR_F32), B.DR_F32, workspace=ws,
+                        tuning=_scan_tuning(form))
+    assert np.array_equal(dev_to_np(out), np.arange(1, 13001, dtype=np.float32))
     assert ws.device_status() == 0
