@@ -23,7 +23,6 @@ workload. Inputs are resident in HBM before timing starts.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -32,21 +31,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2406_00158_amd.traffic import sources_hash  # noqa: E402 (no torch import)
+
 METRIC = "effective HBM GB/s (% of peak) for fused reduce/scan; batched+compensated vs plain"
 HBM_PEAK_GBS = 8000.0
 N = 1 << 28
 SEGMENTS = 8
 SCALAR = 3.0
-KERNEL_SOURCES = ["dr_device.hpp", "dr_internal.hpp", "dr_combine.hpp", "k_elementwise.hip", "k_reduce.hip",
-                  "k_scan.hip", "k_plan.hip", "dr_api.cpp"]
-
-
-def sources_hash() -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2406_00158_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel: str):
@@ -59,37 +50,39 @@ def load_traffic(kernel: str):
     except (OSError, ValueError):
         return None
     if rec.get("sources") != sources_hash():
-        return None
+        return None   # counters taken on other kernel sources
     ent = rec.get("kernels", {}).get(kernel)
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def cpu_baseline(sample_log2: int = 27) -> dict:
-    """The serial oracle (plain C, one thread) on the first 2^sample_log2
-    elements of the same workload, same five steps."""
+def cpu_baseline(reps: int = 3) -> dict:
+    """The serial oracle (plain C, one thread) on the same workload (all
+    2^28 elements, same segments), the same five steps, `reps` times."""
     import numpy as np
 
     import oracle as O
     from paper_2406_00158_amd import inputs as I
 
-    n = 1 << sample_log2
-    t = I.triad(n=n, segments=SEGMENTS)
+    t = I.triad(n=N, segments=SEGMENTS)
     L = t["lengths"]
     b, c = I.split(t["b"], L), I.split(t["c"], L)
     g = np.ones(1)
     t0 = time.perf_counter()
-    a = O.for_each(b, c, O.F32, O.AXPY, O.F32, alpha=SCALAR)
-    O.reduce(b, c, O.F32, O.MUL)
-    O.scan(a, None, O.F32, O.IDENTITY)
-    O.scan(b, None, O.F32, O.IDENTITY, mode=O.BATCH)
-    O.reduce(b, c, O.F32, O.MUL, mode=O.BATCH)
-    O.reduce_grad(b, c, O.F32, O.MUL, g, 0)
-    O.reduce_grad(b, c, O.F32, O.MUL, g, 1)
-    O.scan(a, None, O.F32, O.IDENTITY, reverse=True)
+    for _ in range(reps):
+        a = O.for_each(b, c, O.F32, O.AXPY, O.F32, alpha=SCALAR)
+        O.reduce(b, c, O.F32, O.MUL)
+        O.scan(a, None, O.F32, O.IDENTITY)
+        O.scan(b, None, O.F32, O.IDENTITY, mode=O.BATCH)
+        O.reduce(b, c, O.F32, O.MUL, mode=O.BATCH)
+        O.reduce_grad(b, c, O.F32, O.MUL, g, 0)
+        O.reduce_grad(b, c, O.F32, O.MUL, g, 1)
+        O.scan(a, None, O.F32, O.IDENTITY, reverse=True)
+        del a
     dt = time.perf_counter() - t0
-    return {"value": round(step_bytes(n) / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"the same five steps on the first 2^{sample_log2} elements ({SEGMENTS} segments), "
-                      f"serial C oracle (gcc -O2, binary64/int64), one thread, {dt:.2f} s"}
+    return {"value": round(reps * step_bytes(N) / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole workload (2^28 elements, {SEGMENTS} segments), the same five steps "
+                      f"{reps} times, serial C oracle (gcc -O2, binary64/int64 arithmetic), one thread, "
+                      f"{dt:.2f} s"}
 
 
 BYTES_PER_ELEM = {"for_each": 12, "reduce": 8, "scan": 8, "batched": 12, "backward_mul": 16, "backward_scan": 8}
@@ -215,12 +208,18 @@ def main() -> int:
     plain_ms = e0.elapsed_time(e1) / 10
     flags = ws.device_status() | ws_b.device_status()
 
-    dom = max(per_op_ms, key=per_op_ms.get)
-    kernel_name = {"for_each": "k_for_each", "reduce": "k_reduce", "scan": "k_scan", "batched": "k_scan",
-                   "backward_mul": "k_broadcast_mul", "backward_scan": "k_scan"}[dom]
+    # roofline: the longest-running single kernel of the step. The ops
+    # below are one main kernel launch each (the reduce adds a 2-5 us
+    # counter-zeroing prologue), so HIP events around the op time that
+    # kernel; the scans are several passes in one call and are reported per
+    # op (per_op) and per kernel in the committed kernel-trace profile.
+    single = {"for_each": "k_for_each", "reduce": "k_reduce_stream", "backward_mul": "k_broadcast_mul"}
+    dom = max(single, key=lambda k: per_op_ms[k])
+    kernel_name = single[dom]
     achieved = BYTES_PER_ELEM[dom] * N / (per_op_ms[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(f"{dom}")}
+    roofline = {"bound": "hbm", "kernel": kernel_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kernel_name),
+                "algorithmic_bytes_per_launch": BYTES_PER_ELEM[dom] * N}
 
     per_op = {k: {"ms": round(v, 4), "GB/s": round(BYTES_PER_ELEM[k] * N / (v * 1e-3) / 1e9, 1),
                   "frac_of_peak": round(BYTES_PER_ELEM[k] * N / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -247,6 +246,7 @@ def main() -> int:
                                "backward (dot adjoint + reverse scan)",
                    "elements": N, "segments": SEGMENTS, "bytes_per_step": step_bytes(N),
                    "frac_of_peak": round(value / HBM_PEAK_GBS, 4), "dominant_kernel": kernel_name,
+                   "dominant_op": max(per_op_ms, key=per_op_ms.get),
                    "per_op": per_op, "device_fault_flags": flags, "wall_s": round(wall, 3)},
         "roofline": roofline,
         "cpu_baseline": None,

@@ -26,7 +26,7 @@ struct Header {
     uint32_t error;      // DR_DEVFLAG_* bits, sticky until dr_device_status
     uint32_t epoch;      // launches on this workspace; bumped by each launch's prologue
     uint32_t plan_tag;   // tag of the launch that wrote the plan words
-    uint32_t ticket;     // next tile index handed out by the streaming scan; zeroed by the prologue
+    uint32_t pad0;
     uint64_t plan_rows;  // key of the plan built by dr_plan
     int64_t plan_m;
     int64_t plan_tile;

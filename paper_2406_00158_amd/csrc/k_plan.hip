@@ -128,7 +128,6 @@ __global__ __launch_bounds__(256) void k_prologue(uint8_t* ws, uint64_t off_g, u
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         Header* h = (Header*)ws;
         h->epoch = h->epoch + 1u;
-        h->ticket = 0u;
     }
     uint32_t* g = (uint32_t*)(ws + off_g);
     uint32_t* u = (uint32_t*)(ws + off_u);
