@@ -92,6 +92,205 @@ def step_bytes(n: int) -> int:
     return n * sum(BYTES_PER_ELEM.values())
 
 
+def configs_report(reps: int) -> int:
+    """Every workload of the hot path at its full size, timed alone: the
+    median, 10th and 90th percentile of `reps` launches (HIP events on the
+    launch stream), as GB/s at algorithmic bytes, fraction of the 8 TB/s
+    peak and of a plain copy measured here. One JSON line per case."""
+    import numpy as np
+    import torch
+
+    from paper_2406_00158_amd import binding as B
+    from paper_2406_00158_amd import inputs as I
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def to_dev(a):
+        if a.dtype == np.uint16:
+            return torch.from_numpy(a.view(np.int16)).to(dev).view(torch.bfloat16)
+        return torch.from_numpy(a).to(dev)
+
+    def pieces(t, lengths):
+        out, o = [], 0
+        for n in lengths:
+            out.append(t[o:o + n])
+            o += n
+        return out
+
+    def timed(fn, n_reps, warm=3):
+        for _ in range(warm):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_reps)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+        pick = lambda q: ms[min(len(ms) - 1, int(q * (len(ms) - 1) + 0.5))]
+        return pick(0.5), pick(0.1), pick(0.9)
+
+    copy_gbs = [None]
+    ws = B.Workspace(dev)
+
+    def report(cfg, case, nbytes, fn, n_reps=reps, latency=False, note=None):
+        med, p10, p90 = timed(fn, n_reps)
+        gbs = nbytes / (med * 1e-3) / 1e9
+        line = {"config": cfg, "case": case, "median_us": round(med * 1e3, 1), "p10_us": round(p10 * 1e3, 1),
+                "p90_us": round(p90 * 1e3, 1), "algorithmic_bytes": nbytes, "GB/s": round(gbs, 1),
+                "frac_of_peak": None if latency else round(gbs / HBM_PEAK_GBS, 4),
+                "frac_of_copy": None if (latency or copy_gbs[0] is None) else round(gbs / copy_gbs[0], 4),
+                "reps": n_reps}
+        if note:
+            line["note"] = note
+        print(json.dumps(line), flush=True)
+        return gbs
+
+    # copy reference: for_each identity, 2^28 binary32 (1 GiB each way)
+    src = torch.rand(N, device=dev)
+    dst = torch.empty_like(src)
+    tcp = B.segments([[src]], [[dst]])
+    copy_gbs[0] = report("copy", "for_each identity 2^28 f32", 8 * N,
+                         lambda: B.dr_for_each(tcp, B.make_view("identity", B.DR_F32), B.DR_F32, host_check=False))
+    del src, dst, tcp
+
+    # C1 tiny: 2^20, 4 unequal segments, separate allocations and one carved buffer
+    t = I.tiny()
+    L = t["lengths"]
+    n = sum(L)
+    for layout in ("separate", "carved"):
+        if layout == "separate":
+            x = [to_dev(p.copy()) for p in I.split(t["x"], L)]
+            y = [to_dev(p.copy()) for p in I.split(t["y"], L)]
+            k = [to_dev(p.copy()) for p in I.split(t["k"], L)]
+        else:
+            x, y, k = (pieces(to_dev(t[nm]), L) for nm in ("x", "y", "k"))
+        res = torch.zeros(1, dtype=torch.float64, device=dev)
+        resi = torch.zeros(1, dtype=torch.int64, device=dev)
+        ko = [torch.empty(p.numel(), dtype=torch.int32, device=dev) for p in k]
+        tdot, tk, tks = B.segments([x, y]), B.segments([k]), B.segments([k], [ko])
+        report("C1 tiny " + layout, "dot compensated", 8 * n, lambda: B.dr_transform_reduce(
+            tdot, B.make_view("mul", B.DR_F32), B.DR_ACC_COMPENSATED, 0.0, res, workspace=ws, host_check=False),
+            latency=True)
+        report("C1 tiny " + layout, "int32 scan -> int32", 8 * n, lambda: B.dr_inclusive_scan(
+            tks, B.make_view("identity", B.DR_I32), B.DR_I32, workspace=ws, host_check=False), latency=True)
+        report("C1 tiny " + layout, "int sum", 4 * n, lambda: B.dr_transform_reduce(
+            tk, B.make_view("identity", B.DR_I32), 0, 0, resi, workspace=ws, host_check=False), latency=True)
+    del t
+
+    # C2 triad + dot: 2^28, 8 equal segments
+    t = I.triad()
+    L = t["lengths"]
+    b, c = to_dev(t["b"]), to_dev(t["c"])
+    a = torch.empty_like(b)
+    del t
+    res = torch.zeros(1, dtype=torch.float64, device=dev)
+    ttr, tdot = B.segments([pieces(b, L), pieces(c, L)], [pieces(a, L)]), B.segments([pieces(b, L), pieces(c, L)])
+    report("C2 triad", "for_each a = b + 3c", 12 * N, lambda: B.dr_for_each(
+        ttr, B.make_view("axpy", B.DR_F32, SCALAR), B.DR_F32, host_check=False))
+    for acc in ("compensated", "plain"):
+        report("C2 triad", f"dot {acc}", 8 * N, lambda: B.dr_transform_reduce(
+            tdot, B.make_view("mul", B.DR_F32), B.ACCS[acc], 0.0, res, workspace=ws, host_check=False))
+    del a, b, c, ttr, tdot
+
+    # C3 scans: int32 2^30 (16 Dirichlet segments) and binary32 2^28 (its own 16)
+    t = I.scan_int()
+    L = t["lengths"]
+    k = to_dev(t["k"])
+    del t
+    nk = k.numel()
+    for odt, ob in ((B.DR_I64, 8), (B.DR_I32, 4)):
+        out = torch.empty(nk, dtype=B.TORCH_DTYPE[odt], device=dev)
+        tab = B.segments([pieces(k, L)], [pieces(out, L)])
+        report("C3 scan", f"int32 2^30 -> {'int64' if odt == B.DR_I64 else 'int32 (wrap)'}", (4 + ob) * nk,
+               lambda: B.dr_inclusive_scan(tab, B.make_view("identity", B.DR_I32), odt, workspace=ws,
+                                           host_check=False), n_reps=max(5, reps // 4))
+        del out, tab
+    del k
+    t = I.scan_fp()
+    L = t["lengths"]
+    x = to_dev(t["x"])
+    del t
+    out = torch.empty_like(x)
+    tab = B.segments([pieces(x, L)], [pieces(out, L)])
+    for fl, nm in ((0, "binary64 carries"), (B.DR_SCAN_CARRY_F32, "binary32 carries")):
+        report("C3 scan", f"f32 2^28, {nm}", 8 * x.numel(), lambda: B.dr_inclusive_scan(
+            tab, B.make_view("identity", B.DR_F32), B.DR_F32, fl, workspace=ws, host_check=False))
+    del x, out, tab
+
+    # C4 precision: 2^29 mixture, binary32 and bfloat16, plain vs compensated
+    t = I.precision()
+    L = t["lengths"]
+    n4 = sum(L)
+    for dt, (xs, ys), eb in (("f32", (t["x"], t["y"]), 4), ("bf16", (t["x_bf16"], t["y_bf16"]), 2)):
+        xd, yd = to_dev(xs), to_dev(ys)
+        bdt = B.DR_F32 if dt == "f32" else B.DR_BF16
+        t1, t2 = B.segments([pieces(xd, L)]), B.segments([pieces(xd, L), pieces(yd, L)])
+        for acc in ("compensated", "plain"):
+            report("C4 precision", f"{dt} sum of squares {acc}", eb * n4, lambda: B.dr_transform_reduce(
+                t1, B.make_view("square", bdt), B.ACCS[acc], 0.0, res, workspace=ws, host_check=False))
+            report("C4 precision", f"{dt} dot {acc}", 2 * eb * n4, lambda: B.dr_transform_reduce(
+                t2, B.make_view("mul", bdt), B.ACCS[acc], 0.0, res, workspace=ws, host_check=False))
+        del xd, yd, t1, t2
+    del t
+
+    # C5 batch: 10,000 ragged ranges (2^28 total), fused scan + dot, backward
+    t = I.batch()
+    L = t["lengths"]
+    x, y = to_dev(t["x"]), to_dev(t["y"])
+    del t
+    n5 = x.numel()
+    s5 = torch.empty_like(x)
+    r5 = torch.zeros(len(L), dtype=torch.float64, device=dev)
+    ws5 = B.Workspace(dev)
+    tab = B.segments([pieces(x, L), pieces(y, L)], [pieces(s5, L)], mode="batch")
+    tsc = B.segments([pieces(x, L)], [pieces(s5, L)], mode="batch")
+    tdt = B.segments([pieces(x, L), pieces(y, L)], mode="batch")
+    vid, vmul = B.make_view("identity", B.DR_F32), B.make_view("mul", B.DR_F32)
+    fused = lambda: B.dr_scan_reduce(tab, vid, vmul, B.DR_ACC_COMPENSATED, 0.0, r5, workspace=ws5,
+                                     host_check=False)
+    report("C5 batch", "fused scan + dot, eager", 12 * n5, fused)
+    fused()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fused()
+    torch.cuda.current_stream().wait_stream(side)
+    with torch.cuda.graph(g):
+        fused()
+    report("C5 batch", "fused scan + dot, hipGraph replay", 12 * n5, g.replay)
+    # one workspace per table: a workspace holds the plan of one large table
+    ws_s, ws_d, ws_b, ws_r = (B.Workspace(dev) for _ in range(4))
+    report("C5 batch", "unfused: scan, then dot (two calls)", 16 * n5, lambda: (
+        B.dr_inclusive_scan(tsc, vid, B.DR_F32, workspace=ws_s, host_check=False),
+        B.dr_transform_reduce(tdt, vmul, B.DR_ACC_COMPENSATED, 0.0, r5, workspace=ws_d, host_check=False)))
+    gx, gy = torch.empty_like(x), torch.empty_like(y)
+    gg = torch.ones(len(L), dtype=torch.float64, device=dev)
+    tbm = B.segments([pieces(x, L), pieces(y, L)], [pieces(gx, L), pieces(gy, L)], mode="batch")
+    trs = B.segments([pieces(s5, L)], [pieces(gx, L)], mode="batch")
+    report("C5 batch", "backward: dot adjoint (broadcast multiply)", 16 * n5, lambda: B.dr_broadcast_mul(
+        tbm, vmul, gg, 2, workspace=ws_b, host_check=False))
+    report("C5 batch", "backward: scan adjoint (reverse scan)", 8 * n5, lambda: B.dr_inclusive_scan(
+        trs, vid, B.DR_F32, B.DR_SCAN_REVERSE, workspace=ws_r, host_check=False))
+    # one call per range, for the launch-count contrast (the batched call is one)
+    per = [(B.segments([[xs], [ys]], [[ss]]), r5[i:i + 1]) for i, (xs, ys, ss) in
+           enumerate(zip(pieces(x, L), pieces(y, L), pieces(s5, L)))]
+    ws1 = B.Workspace(dev)
+    ws1.for_call(B.DR_ALGO_SCAN_REDUCE, per[int(np.argmax(L))][0], vid, None)
+    report("C5 batch", "fused scan + dot, one call per range (10,000 calls)", 12 * n5, lambda: [
+        B.dr_scan_reduce(tb, vid, vmul, B.DR_ACC_COMPENSATED, 0.0, rr, workspace=ws1, host_check=False)
+        for tb, rr in per], n_reps=2)
+    flags = 0
+    for w_ in (ws, ws5, ws1, ws_s, ws_d, ws_b, ws_r):
+        flags |= w_.device_status()
+    print(json.dumps({"device_fault_flags": flags}), flush=True)
+    return 0 if flags == 0 else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,11 +300,17 @@ def main() -> int:
     ap.add_argument("--copy-only", action="store_true",
                     help="run only a plain copy (for_each identity, 2^28 f32) K times: the known-size "
                          "kernel that calibrates the HBM byte counters")
+    ap.add_argument("--configs", action="store_true",
+                    help="time every workload (tiny, triad, scans, precision, batch) alone at full size and "
+                         "print one JSON line per case instead of the step line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
               "path would shard); run with --gpus 1", file=sys.stderr)
         return 2
+
+    if args.configs:
+        return configs_report(max(args.steps, 5))
 
     import torch
 

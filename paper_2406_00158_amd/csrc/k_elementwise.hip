@@ -119,7 +119,7 @@ __device__ __forceinline__ double dview(typename elem<IDT>::T x, typename elem<I
     else return which == 0 ? 1.0 : alpha;
 }
 
-template <int IDT, int OP, int ITEMS>
+template <int IDT, int OP, int ITEMS, int NOUT>
 __global__ __launch_bounds__(kBlock) void k_broadcast_mul(LaunchArgs a) {
     constexpr int V = vwidth<IDT>();
     constexpr int SLOTS = ITEMS / V;
@@ -140,7 +140,8 @@ __global__ __launch_bounds__(kBlock) void k_broadcast_mul(LaunchArgs a) {
     vec<IDT> x[SLOTS], y[SLOTS];
     if constexpr (OP != DR_OP_IDENTITY) load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, false);
     if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, false);
-    for (int which = 0; which < a.nout; ++which) {
+#pragma unroll
+    for (int which = 0; which < NOUT; ++which) {
         void* out = which == 0 ? si.out0 : si.out1;
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
@@ -165,8 +166,10 @@ hipError_t launch_for_each(const LaunchArgs& a, int64_t grid, hipStream_t stream
 
 template <int IDT, int OP, int ITEMS>
 hipError_t launch_broadcast_mul(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
-    hipLaunchKernelGGL((k_broadcast_mul<IDT, OP, ITEMS>), dim3((uint32_t)grid), dim3(kBlock), 0,
-                       stream, a);
+    if (a.nout == 2)
+        hipLaunchKernelGGL((k_broadcast_mul<IDT, OP, ITEMS, 2>), dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_broadcast_mul<IDT, OP, ITEMS, 1>), dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -205,6 +208,7 @@ LaunchFn find_for_each(int in_dt, int out_dt, int op, int items) {
 
 LaunchFn find_broadcast_mul(int in_dt, int op, int items) {
     DR_BM_OPS(DR_F32, 16)
+    DR_BM_OPS(DR_F32, 32)
     DR_BM_OPS(DR_BF16, 16)
     DR_BM_OPS(DR_F64, 16)
     return nullptr;
