@@ -16,10 +16,11 @@
  *    Here that is the view descriptor, evaluated in registers inside the one
  *    kernel that runs the algorithm (no intermediate array).
  *  - The algorithms are for_each, reduce and inclusive_scan over the
- *    segments (section 4.3; Algorithms 3 and 4). Here each is a single
- *    launch over all segments; the scan's cross-segment offsets travel
- *    through a decoupled look-back carry chain inside that launch instead of
- *    the paper's second pass.
+ *    segments (section 4.3; Algorithms 3 and 4). Here each call covers all
+ *    segments at once (the paper launches per segment). The scan takes its
+ *    cross-segment offsets from a read-only first pass of tile totals and
+ *    writes every output once (the paper's second pass re-reads and
+ *    re-writes the output).
  *
  * Conventions shared by every entry point:
  *  - Ownership: the caller owns every buffer (inputs, outputs, the device
@@ -177,13 +178,12 @@ typedef struct dr_tuning {
     int32_t reserved;   /* must be 0 */
 } dr_tuning;
 
-/* dr_tuning.flags: one workgroup per tile instead of the default streaming
- * grid of resident workgroups. For a CONCAT transform_reduce: a per-tile
- * combine instead of each workgroup summing many tiles and combining once.
- * For inclusive_scan / scan_reduce: tiles in block-index order, each
- * workgroup looking back with all its threads, instead of workgroups that
- * take tiles from a counter and overlap each tile's look-back with the
- * loads of their next tile. */
+/* dr_tuning.flags: one workgroup per tile, single pass. For a CONCAT
+ * transform_reduce: a per-tile combine instead of a resident grid whose
+ * workgroups each sum many tiles and combine once. For inclusive_scan /
+ * scan_reduce: one kernel whose tiles, in block-index order, take their
+ * carries from a decoupled look-back over their predecessors, instead of
+ * the default read-only tile-totals pass followed by the apply pass. */
 enum { DR_TUNE_TILE_PER_BLOCK = 1 };
 
 /* Library version (DR_ABI_VERSION). Never fails. */
@@ -257,8 +257,12 @@ dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_
  * view over positions 0..i (CONCAT: across segments; BATCH: within the
  * element's segment), or over positions i.. (DR_SCAN_REVERSE).
  * The offset of a segment is the total of the segments before it (0 for the
- * first), reached through a decoupled look-back over tiles in the same
- * launch. Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
+ * first). By default the call runs three kernels: tile totals (reads the
+ * input), a scan of per-chunk totals, and the tile scans plus carries
+ * (reads the input again, writes the output once); carries are sums in a
+ * fixed order, so results repeat from run to run. With
+ * DR_TUNE_TILE_PER_BLOCK it is one kernel whose tiles take their carries
+ * from a decoupled look-back. Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
  * (exact modulo 2^32), F32 -> F32 and BF16 -> F32 (binary32 inside a tile,
  * binary64 carries unless DR_SCAN_CARRY_F32), F64 -> F64.
  * In-place (out[0] == in[0], same dtype size) is allowed; other overlap
@@ -269,14 +273,15 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
                             const dr_tuning* tuning, void* stream);
 
 /*
- * Fused inclusive_scan + transform_reduce over the same rows in one launch,
- * every input element read once: out[0] receives the inclusive scan of the
+ * Fused inclusive_scan + transform_reduce over the same rows in one call
+ * (the reduction runs inside the scan's apply pass, so in[1] is read once):
+ * out[0] receives the inclusive scan of the
  * scan view (identity of in[0]), and `result` the reduction of the reduce
  * view (mul over in[0], in[1]); both per segment in BATCH mode. Types:
  * F32 in -> F32 scan out (binary64 carries) and a binary64 result with
  * `acc` accumulation; F64 in -> F64 scan out and result (`acc` ignored).
  * `init` is a host double. This is the batched form: thousands of ragged
- * ranges in BATCH mode are one launch (capturable in a hipGraph).
+ * ranges in BATCH mode are one call (capturable in a hipGraph).
  */
 dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view,
                          const dr_view* reduce_view, int32_t acc, const void* init,
@@ -295,6 +300,60 @@ dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view,
 dr_status dr_broadcast_mul(const dr_table* table, const dr_view* view, const double* g,
                            int32_t n_grads, void* workspace, size_t ws_bytes,
                            const dr_tuning* tuning, void* stream);
+
+/* ---- Segment algebra (host side; section 4.4) ------------------------------
+ * Views that change which elements or which segment boundaries a call sees.
+ * They only compute new segment lists on the host; the kernels above then
+ * run on the result unchanged. */
+
+/* One segment of a single distributed range: `length` elements at `ptr`
+ * (device memory; only the address is used here). */
+typedef struct dr_span {
+    void* ptr;
+    int64_t length;
+} dr_span;
+
+/* A distributed range (section 3): its segments in order, each of elements
+ * of `elem_size` bytes. `spans` is a host array. */
+typedef struct dr_range {
+    const dr_span* spans;
+    int64_t n_spans;
+    int32_t elem_size;   /* bytes per element, > 0 */
+    int32_t reserved;    /* must be 0 */
+} dr_range;
+
+/*
+ * take / drop (section 4.4, "Take and Drop": trim_segments): the segments
+ * of `r` restricted to the elements [first, last) of its concatenation, in
+ * order; segments that keep no element are left out. take(l) is [0, l),
+ * drop(f) is [f, total). `first` and `last` are clamped to [0, total]; last
+ * <= first gives an empty range. Writes at most r->n_spans spans to `out`
+ * (host array of `capacity` entries) and their count to *n_out. Host only:
+ * no device access, nothing enqueued. Errors (DR_ERR_INVALID_ARG): NULL
+ * pointers, a negative length, elem_size <= 0, a non-zero reserved field,
+ * capacity smaller than the result.
+ */
+dr_status dr_trim_segments(const dr_range* r, int64_t first, int64_t last, dr_span* out,
+                           int64_t capacity, int64_t* n_out);
+
+/*
+ * zip of ranges whose segments are not aligned (section 4.4, "Zip"): the
+ * coarsest common refinement of the segment boundaries of `n_in` input
+ * ranges (1..DR_MAX_ARITY) and `n_out` output ranges (0..DR_MAX_OUTPUTS), as
+ * segment-table rows. Walking all ranges together, each row takes from every
+ * range the largest piece that stays inside that range's current segment,
+ * i.e. the minimum of their remaining lengths; row k's in[i] / out[j] point
+ * at the k-th piece of input i / output j, and `length` is the common piece
+ * length. Empty segments are stepped over and produce no row. The zip ends
+ * with the shortest range; *length receives its element count. At most the
+ * total number of spans of all ranges rows are written to `rows` (host
+ * array of `capacity` entries; unused in/out slots are NULL); *n_rows
+ * receives the count. Copy the rows to the device for dr_table.rows and
+ * pass them as dr_table.host_rows. Host only. Errors as dr_trim_segments,
+ * plus n_in / n_out out of range.
+ */
+dr_status dr_zip_segments(const dr_range* ins, int32_t n_in, const dr_range* outs, int32_t n_out,
+                          dr_segment* rows, int64_t capacity, int64_t* n_rows, int64_t* length);
 
 /*
  * Read and clear the device fault flag of a workspace. Synchronises

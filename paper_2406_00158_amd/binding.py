@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libdr.so")
 
 # --- constants mirrored from include/dr.h ------------------------------------
 DR_OK = 0
+DR_ERR_INVALID_ARG, DR_ERR_UNSUPPORTED, DR_ERR_WORKSPACE, DR_ERR_HIP, DR_ERR_NOT_ALIGNED, DR_ERR_DEVICE = \
+    -1, -2, -3, -4, -5, -6
 DR_I32, DR_F32, DR_BF16, DR_F64, DR_I64 = 0, 1, 2, 3, 4
 DR_OP_IDENTITY, DR_OP_SQUARE, DR_OP_MUL, DR_OP_AXPY = 0, 1, 2, 3
 DR_ACC_PLAIN, DR_ACC_COMPENSATED = 0, 1
@@ -56,6 +58,15 @@ class dr_table(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class dr_span(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("length", ctypes.c_int64)]
+
+
+class dr_range(ctypes.Structure):
+    _fields_ = [("spans", ctypes.POINTER(dr_span)), ("n_spans", ctypes.c_int64),
+                ("elem_size", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class dr_tuning(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("items_per_thread", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -67,7 +78,7 @@ assert ctypes.sizeof(dr_view) == 24
 EXPORTS = ["dr_abi_version", "dr_status_string", "dr_last_error", "dr_tuning_supported",
            "dr_workspace_bytes", "dr_workspace_init", "dr_plan", "dr_for_each",
            "dr_transform_reduce", "dr_inclusive_scan", "dr_scan_reduce", "dr_broadcast_mul",
-           "dr_device_status"]
+           "dr_device_status", "dr_trim_segments", "dr_zip_segments"]
 
 _lib = None
 
@@ -103,6 +114,9 @@ def lib() -> ctypes.CDLL:
     L.dr_scan_reduce.argtypes = [TP, VP, VP, i32, P, P, u32, P, S, UP, P]
     L.dr_broadcast_mul.argtypes = [TP, VP, P, i32, P, S, UP, P]
     L.dr_device_status.argtypes = [P, ctypes.POINTER(u32), P]
+    RP, I64P = ctypes.POINTER(dr_range), ctypes.POINTER(i64)
+    L.dr_trim_segments.argtypes = [RP, i64, i64, ctypes.POINTER(dr_span), i64, I64P]
+    L.dr_zip_segments.argtypes = [RP, i32, RP, i32, ctypes.POINTER(dr_segment), i64, I64P, I64P]
     for name in EXPORTS[3:]:
         if name not in ("dr_status_string", "dr_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -335,3 +349,83 @@ def dr_broadcast_mul(table: Table, view: dr_view, g: torch.Tensor, n_grads: int,
 def dr_device_status(workspace: Workspace) -> int:
     """Raw device fault flags of the workspace (0 = none); clears them."""
     return workspace.device_status()
+
+
+# --- segment algebra (section 4.4): take / drop and zip of non-aligned ranges ----
+
+def _range_of(segs) -> tuple[dr_range, ctypes.Array]:
+    """A dr_range over a list of 1-D contiguous tensors (one distributed
+    range); returns the struct and the span array it points to."""
+    if not segs:
+        raise ValueError("a range needs at least one segment list entry (it may be empty)")
+    es = segs[0].element_size()
+    spans = (dr_span * len(segs))()
+    for k, t in enumerate(segs):
+        if t.dim() != 1 or not t.is_contiguous() or t.element_size() != es:
+            raise ValueError(f"segment {k}: 1-D contiguous tensors of one element size")
+        spans[k].ptr = t.data_ptr() if t.numel() else None
+        spans[k].length = t.numel()
+    return dr_range(spans, len(segs), es, 0), spans
+
+
+def _view_at(segs, k0: int, ptr: int, length: int):
+    """The tensor view of `length` elements at device address `ptr`, which
+    lies in one of segs[k0:]; returns (view, index of that segment)."""
+    for k in range(k0, len(segs)):
+        t = segs[k]
+        if t.numel() and t.data_ptr() <= ptr < t.data_ptr() + t.numel() * t.element_size():
+            off = (ptr - t.data_ptr()) // t.element_size()
+            return t[off:off + length], k
+    raise RuntimeError("span outside the range's segments")
+
+
+def trim_segments(segs, first: int, last: int) -> list:
+    """The segments (tensor views) of the range restricted to its elements
+    [first, last) (section 4.4, "Take and Drop"), computed by
+    dr_trim_segments."""
+    r, keep = _range_of(segs)
+    out = (dr_span * max(1, len(segs)))()
+    n = ctypes.c_int64(0)
+    check(lib().dr_trim_segments(ctypes.byref(r), first, last, out, len(segs), ctypes.byref(n)))
+    views, k = [], 0
+    for i in range(n.value):
+        v, k = _view_at(segs, k, out[i].ptr, out[i].length)
+        views.append(v)
+    return views
+
+
+def take(segs, n: int) -> list:
+    """The first n elements of a segmented range."""
+    return trim_segments(segs, 0, n)
+
+
+def drop(segs, n: int) -> list:
+    """All but the first n elements of a segmented range."""
+    return trim_segments(segs, n, sum(t.numel() for t in segs))
+
+
+def zip_segments(inputs, outputs=None, mode: int | str = DR_MODE_CONCAT) -> Table:
+    """Table of the zip of ranges whose segments need not be aligned
+    (section 4.4, "Zip"): `inputs` / `outputs` are lists of ranges, each a
+    list of 1-D tensors; dr_zip_segments refines their boundaries into
+    aligned rows. The zip is as long as the shortest range."""
+    outputs = outputs or []
+    if not inputs or len(inputs) > DR_MAX_ARITY or len(outputs) > DR_MAX_OUTPUTS:
+        raise ValueError("between 1 and 4 input ranges and at most 2 output ranges")
+    rin = [_range_of(r) for r in inputs]
+    rout = [_range_of(r) for r in outputs]
+    ins = (dr_range * len(rin))(*[r for r, _ in rin])
+    outs = (dr_range * max(1, len(rout)))(*[r for r, _ in rout])
+    cap = sum(len(r) for r in inputs) + sum(len(r) for r in outputs)
+    rows = (dr_segment * max(1, cap))()
+    n, total = ctypes.c_int64(0), ctypes.c_int64(0)
+    check(lib().dr_zip_segments(ins, len(rin), outs, len(rout), rows, cap, ctypes.byref(n), ctypes.byref(total)))
+    m = n.value
+    device = inputs[0][0].device
+    host = (dr_segment * max(1, m))()
+    ctypes.memmove(host, rows, ctypes.sizeof(dr_segment) * m)
+    raw = np.frombuffer(bytes(host), dtype=np.uint8)[: 64 * m]
+    dev = torch.from_numpy(raw.copy()).to(device) if m else torch.empty(0, dtype=torch.uint8, device=device)
+    mode = MODES[mode] if isinstance(mode, str) else mode
+    return Table(m, mode, device, host, dev, total.value, [list(inputs), list(outputs)])
+

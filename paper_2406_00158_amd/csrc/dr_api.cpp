@@ -504,3 +504,121 @@ dr_status dr_device_status(void* ws, uint32_t* flags, void* stream) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Segment algebra (section 4.4): host-only computations on segment lists
+// ---------------------------------------------------------------------------
+
+namespace {
+
+dr_status check_range(const dr_range* r, const char* what) {
+    if (!r) return fail(DR_ERR_INVALID_ARG, "%s is NULL", what);
+    if (r->elem_size <= 0) return fail(DR_ERR_INVALID_ARG, "%s: elem_size must be positive", what);
+    if (r->reserved != 0) return fail(DR_ERR_INVALID_ARG, "%s: reserved field must be 0", what);
+    if (r->n_spans < 0) return fail(DR_ERR_INVALID_ARG, "%s: negative span count", what);
+    if (r->n_spans > 0 && !r->spans) return fail(DR_ERR_INVALID_ARG, "%s: spans is NULL", what);
+    for (int64_t k = 0; k < r->n_spans; ++k)
+        if (r->spans[k].length < 0) return fail(DR_ERR_INVALID_ARG, "%s: span %lld has a negative length", what,
+                                                (long long)k);
+    return DR_OK;
+}
+
+void* advance(void* p, int64_t elems, int32_t size) {
+    return p ? (void*)((char*)p + elems * (int64_t)size) : nullptr;
+}
+
+}  // namespace
+
+dr_status dr_trim_segments(const dr_range* r, int64_t first, int64_t last, dr_span* out, int64_t capacity,
+                           int64_t* n_out) {
+    dr_status s = check_range(r, "range");
+    if (s) return s;
+    if (!n_out) return fail(DR_ERR_INVALID_ARG, "n_out is NULL");
+    int64_t total = 0;
+    for (int64_t k = 0; k < r->n_spans; ++k) total += r->spans[k].length;
+    first = std::min(std::max<int64_t>(first, 0), total);
+    last = std::min(std::max<int64_t>(last, 0), total);
+    // count first, so that a too-small `out` is rejected before any write
+    int64_t n = 0, o = 0;
+    for (int64_t k = 0; k < r->n_spans; ++k) {
+        const int64_t b = std::max(o, first), e = std::min(o + r->spans[k].length, last);
+        if (e > b) ++n;
+        o += r->spans[k].length;
+    }
+    if (n > 0 && !out) return fail(DR_ERR_INVALID_ARG, "out is NULL");
+    if (n > capacity) return fail(DR_ERR_INVALID_ARG, "capacity %lld < %lld spans", (long long)capacity,
+                                  (long long)n);
+    int64_t i = 0;
+    o = 0;
+    for (int64_t k = 0; k < r->n_spans; ++k) {
+        const int64_t len = r->spans[k].length;
+        const int64_t b = std::max(o, first), e = std::min(o + len, last);
+        if (e > b) out[i++] = dr_span{advance(r->spans[k].ptr, b - o, r->elem_size), e - b};
+        o += len;
+    }
+    *n_out = n;
+    return ok();
+}
+
+dr_status dr_zip_segments(const dr_range* ins, int32_t n_in, const dr_range* outs, int32_t n_out,
+                          dr_segment* rows, int64_t capacity, int64_t* n_rows, int64_t* length) {
+    if (n_in < 1 || n_in > DR_MAX_ARITY) return fail(DR_ERR_INVALID_ARG, "n_in must be 1..%d", DR_MAX_ARITY);
+    if (n_out < 0 || n_out > DR_MAX_OUTPUTS) return fail(DR_ERR_INVALID_ARG, "n_out must be 0..%d", DR_MAX_OUTPUTS);
+    if (!ins || (n_out > 0 && !outs)) return fail(DR_ERR_INVALID_ARG, "ranges are NULL");
+    if (!n_rows || !length) return fail(DR_ERR_INVALID_ARG, "n_rows / length is NULL");
+    const int R = n_in + n_out;
+    const dr_range* rs[DR_MAX_ARITY + DR_MAX_OUTPUTS];
+    for (int i = 0; i < n_in; ++i) rs[i] = &ins[i];
+    for (int j = 0; j < n_out; ++j) rs[n_in + j] = &outs[j];
+    for (int i = 0; i < R; ++i) {
+        dr_status s = check_range(rs[i], i < n_in ? "input range" : "output range");
+        if (s) return s;
+    }
+    // Two passes over the same walk: count the rows, then (if they fit) write them.
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t seg[DR_MAX_ARITY + DR_MAX_OUTPUTS] = {0};   // current segment of each range
+        int64_t off[DR_MAX_ARITY + DR_MAX_OUTPUTS] = {0};   // elements already taken from it
+        int64_t n = 0, len = 0;
+        while (true) {
+            bool done = false;
+            int64_t piece = INT64_MAX;
+            for (int i = 0; i < R; ++i) {
+                // step over exhausted (and empty) segments
+                while (seg[i] < rs[i]->n_spans && off[i] == rs[i]->spans[seg[i]].length) {
+                    ++seg[i];
+                    off[i] = 0;
+                }
+                if (seg[i] == rs[i]->n_spans) {
+                    done = true;
+                    break;
+                }
+                piece = std::min(piece, rs[i]->spans[seg[i]].length - off[i]);
+            }
+            if (done) break;
+            if (pass == 1) {
+                dr_segment& row = rows[n];
+                std::memset(&row, 0, sizeof row);
+                for (int i = 0; i < n_in; ++i)
+                    row.in[i] = advance(rs[i]->spans[seg[i]].ptr, off[i], rs[i]->elem_size);
+                for (int j = 0; j < n_out; ++j) {
+                    const int i = n_in + j;
+                    row.out[j] = advance(rs[i]->spans[seg[i]].ptr, off[i], rs[i]->elem_size);
+                }
+                row.length = piece;
+            }
+            for (int i = 0; i < R; ++i) off[i] += piece;
+            ++n;
+            len += piece;
+        }
+        if (pass == 0) {
+            if (n > 0 && !rows) return fail(DR_ERR_INVALID_ARG, "rows is NULL");
+            if (n > capacity)
+                return fail(DR_ERR_INVALID_ARG, "capacity %lld < %lld rows", (long long)capacity, (long long)n);
+        } else {
+            *n_rows = n;
+            *length = len;
+        }
+    }
+    return ok();
+}
+

@@ -72,6 +72,10 @@ __device__ __forceinline__ void combine_member(const LaunchArgs& a, uint32_t tag
     uint32_t* ucnt = (uint32_t*)(a.ws + a.lay.off_ucnt);
     const int64_t TW = a.lay.tile_words, PW = a.lay.part_word;
     const int l = lane_id();
+    if (count == 1) {   // the unit's only member: nothing to wait for or count
+        if (l == 0) write_result<P>(a, unit, partial);
+        return;
+    }
 
     int last_in_group = 0;
     if (l == 0) {

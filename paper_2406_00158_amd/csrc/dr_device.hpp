@@ -152,6 +152,46 @@ __device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
     e = __builtin_fmaf(a, b, -p);
 }
 
+// Compensated binary32 accumulation of the view values of loaded elements
+// into (s, c): s is the running binary32 sum, c collects the exact rounding
+// errors of the products (TwoProduct) and of the additions (TwoSum). The
+// product of two bfloat16 values has at most 16 significant bits and is
+// exact in binary32 (barring underflow below 2^-110, where TwoProduct's
+// error term is itself rounded), so its error term is not formed.
+template <int IDT, int OP, int SLOTS>
+__device__ __forceinline__ void comp_accumulate(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS], float alpha,
+                                                float& s, float& c) {
+    constexpr int V = vwidth<IDT>();
+    constexpr bool EXACT_PROD = IDT == DR_BF16 && (OP == DR_OP_SQUARE || OP == DR_OP_MUL);
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const float x0 = decode<IDT>(x[q].e[e]);
+            float p, pe = 0.0f;
+            if constexpr (OP == DR_OP_IDENTITY) {
+                p = x0;
+            } else if constexpr (OP == DR_OP_SQUARE) {
+                if constexpr (EXACT_PROD) p = x0 * x0;
+                else two_prod(x0, x0, p, pe);
+            } else if constexpr (OP == DR_OP_MUL) {
+                const float x1 = decode<IDT>(y[q].e[e]);
+                if constexpr (EXACT_PROD) p = x0 * x1;
+                else two_prod(x0, x1, p, pe);
+            } else {   // axpy: x0 + alpha * x1
+                float m, me, r;
+                two_prod(alpha, decode<IDT>(y[q].e[e]), m, me);
+                two_sum(x0, m, p, r);
+                pe = r + me;
+            }
+            float err;
+            two_sum(s, p, s, err);
+            if constexpr (OP == DR_OP_IDENTITY || EXACT_PROD) c += err;
+            else c += err + pe;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Cross-workgroup status words
 // ---------------------------------------------------------------------------
@@ -259,6 +299,22 @@ __device__ __forceinline__ int32_t row_shift(const void* in0, int ies) {
     return (int32_t)((b0 % 16) / ies);
 }
 
+// Load of data that no kernel writes while the reading kernel runs (table
+// rows, plan words, the plan key): through the constant address space, so
+// that a wave-uniform address becomes a scalar load. Scalar loads count in
+// their own counter, so such a lookup does not wait behind the wave's
+// outstanding tile loads.
+template <class T>
+__device__ __forceinline__ T ld_const(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // The fields of a table row that the kernels use, read one by one (ops
 // have arity <= 2 and at most 2 outputs).
 struct Row {
@@ -272,11 +328,11 @@ struct Row {
 __device__ __forceinline__ Row load_row(const dr_segment* rows, int64_t k) {
     const dr_segment* p = rows + k;
     Row r;
-    r.in0 = p->in[0];
-    r.in1 = p->in[1];
-    r.out0 = p->out[0];
-    r.out1 = p->out[1];
-    r.n = p->length;
+    r.in0 = ld_const(&p->in[0]);
+    r.in1 = ld_const(&p->in[1]);
+    r.out0 = ld_const(&p->out[0]);
+    r.out1 = ld_const(&p->out[1]);
+    r.n = ld_const(&p->length);
     return r;
 }
 
@@ -351,14 +407,15 @@ struct TileMap {
             return;
         }
         const Header* h = (const Header*)a.ws;
-        ok = a.ws != nullptr && h->plan_m == a.m && h->plan_rows == (uint64_t)(uintptr_t)a.rows &&
-             h->plan_tile == a.tile && h->plan_ies == a.ies && h->plan_total == a.total;
-        plan_tag = ok ? h->plan_tag : 0u;
+        ok = a.ws != nullptr && ld_const(&h->plan_m) == a.m &&
+             ld_const(&h->plan_rows) == (uint64_t)(uintptr_t)a.rows && ld_const(&h->plan_tile) == a.tile &&
+             ld_const(&h->plan_ies) == a.ies && ld_const(&h->plan_total) == a.total;
+        plan_tag = ok ? ld_const(&h->plan_tag) : 0u;
         if (!ok) {
             if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_PLAN);
             return;
         }
-        total_tiles = h->plan_tiles;
+        total_tiles = ld_const(&h->plan_tiles);
         if (total_tiles > a.tmax) {
             if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_TOO_MANY_TILES);
             total_tiles = 0;
@@ -381,10 +438,10 @@ struct TileMap {
         } else {
             const uint64_t* F = (const uint64_t*)(a.ws + a.lay.off_plan_first);
             const uint64_t* tseg = (const uint64_t*)(a.ws + a.lay.off_plan_tseg);
-            const uint64_t wk = tseg[t];
+            const uint64_t wk = ld_const(tseg + uniform64(t));
             const uint32_t kk = (uint32_t)wk;
             const bool kok = (uint32_t)(wk >> 32) == plan_tag && (int64_t)kk < a.m;
-            const uint64_t f0 = kok ? F[kk] : 0, f1 = kok ? F[kk + 1] : 0;
+            const uint64_t f0 = kok ? ld_const(F + kk) : 0, f1 = kok ? ld_const(F + kk + 1) : 0;
             if (!kok || (uint32_t)(f0 >> 32) != plan_tag || (uint32_t)(f1 >> 32) != plan_tag) {
                 if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_PLAN);
                 return false;

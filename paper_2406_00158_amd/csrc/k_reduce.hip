@@ -47,32 +47,8 @@ __device__ __forceinline__ partial_t<IDT> tile_partial(const LaunchArgs& a, cons
 
     P part = (P)0;
     if constexpr (F32PATH && ACC == DR_ACC_COMPENSATED) {
-        const float alpha = (float)a.alpha;
         float s = 0.0f, c = 0.0f;
-#pragma unroll
-        for (int q = 0; q < SLOTS; ++q) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const float x0 = decode<IDT>(x[q].e[e]);
-                float p, pe;
-                if constexpr (OP == DR_OP_IDENTITY) {
-                    p = x0;
-                    pe = 0.0f;
-                } else if constexpr (OP == DR_OP_SQUARE) {
-                    two_prod(x0, x0, p, pe);
-                } else if constexpr (OP == DR_OP_MUL) {
-                    two_prod(x0, decode<IDT>(y[q].e[e]), p, pe);
-                } else {
-                    float m, me, r;
-                    two_prod(alpha, decode<IDT>(y[q].e[e]), m, me);
-                    two_sum(x0, m, p, r);
-                    pe = r + me;
-                }
-                float err;
-                two_sum(s, p, s, err);
-                c += err + pe;
-            }
-        }
+        comp_accumulate<IDT, OP, SLOTS>(x, y, (float)a.alpha, s, c);
         P tp = (double)s + (double)c;   // exact unless s is not finite
         if (!__builtin_isfinite(s)) tp = (double)s;
         const P wsum = wave_sum(tp);
@@ -156,32 +132,8 @@ __device__ __forceinline__ partial_t<IDT> thread_tile_sum(const vec<IDT> (&x)[SL
     constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
     using P = partial_t<IDT>;
     if constexpr ((IDT == DR_F32 || IDT == DR_BF16) && ACC == DR_ACC_COMPENSATED) {
-        const float alpha = (float)alpha_d;
         float s = 0.0f, c = 0.0f;
-#pragma unroll
-        for (int q = 0; q < SLOTS; ++q) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const float x0 = decode<IDT>(x[q].e[e]);
-                float p, pe;
-                if constexpr (OP == DR_OP_IDENTITY) {
-                    p = x0;
-                    pe = 0.0f;
-                } else if constexpr (OP == DR_OP_SQUARE) {
-                    two_prod(x0, x0, p, pe);
-                } else if constexpr (OP == DR_OP_MUL) {
-                    two_prod(x0, decode<IDT>(y[q].e[e]), p, pe);
-                } else {
-                    float m, me, r;
-                    two_prod(alpha, decode<IDT>(y[q].e[e]), m, me);
-                    two_sum(x0, m, p, r);
-                    pe = r + me;
-                }
-                float err;
-                two_sum(s, p, s, err);
-                c += err + pe;
-            }
-        }
+        comp_accumulate<IDT, OP, SLOTS>(x, y, (float)alpha_d, s, c);
         return __builtin_isfinite(s) ? (double)s + (double)c : (double)s;
     } else if constexpr (IDT == DR_F32 || IDT == DR_BF16) {
         const float alpha = (float)alpha_d;

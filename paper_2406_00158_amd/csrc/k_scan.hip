@@ -188,22 +188,14 @@ __device__ __forceinline__ double fused_partial(const vec<IDT> (&x)[SLOTS], cons
         return rs;
     } else {
         float rs = 0.0f, rc = 0.0f;
+        if constexpr (RACC == DR_ACC_COMPENSATED) {
+            comp_accumulate<IDT, ROP, SLOTS>(x, y, 0.0f, rs, rc);
+        } else {
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
+            for (int s = 0; s < SLOTS; ++s) {
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const float x0 = (float)decode<IDT>(x[s].e[e]);
-                const float x1 = (float)decode<IDT>(y[s].e[e]);
-                if constexpr (RACC == DR_ACC_COMPENSATED) {
-                    float p, pe, err;
-                    if constexpr (ROP == DR_OP_MUL) two_prod(x0, x1, p, pe);
-                    else if constexpr (ROP == DR_OP_SQUARE) two_prod(x0, x0, p, pe);
-                    else { p = x0; pe = 0.0f; }
-                    two_sum(rs, p, rs, err);
-                    rc += err + pe;
-                } else {
-                    rs += view_apply<ROP, float>(x0, x1, 0.0f);
-                }
+                for (int e = 0; e < V; ++e)
+                    rs += view_apply<ROP, float>((float)decode<IDT>(x[s].e[e]), (float)decode<IDT>(y[s].e[e]), 0.0f);
             }
         }
         return (double)rs + (double)rc;
