@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 I32, F32, BF16, F64, I64 = 0, 1, 2, 3, 4
 IDENTITY, SQUARE, MUL, AXPY = 0, 1, 2, 3
 CONCAT, BATCH = 0, 1
+SUM, MAX, MIN = 0, 1, 2
 ARITY = {IDENTITY: 1, SQUARE: 1, MUL: 2, AXPY: 2}
 
 _NP_DTYPE = {I32: np.int32, F32: np.float32, BF16: np.uint16, F64: np.float64, I64: np.int64}
@@ -56,6 +57,8 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_reduce.argtypes = [i, PP, PP, I64P, i, i, d, i, i64, d, I64P, DP, DP]
         _lib.oracle_scan.argtypes = [i, PP, PP, PP, PP, I64P, i, i, d, i, i, i]
         _lib.oracle_reduce_grad.argtypes = [i, PP, PP, PP, I64P, i, i, d, i, DP, i]
+        _lib.oracle_reduce_ex.argtypes = [i, PP, PP, I64P, i, i, d, i, i, i, i64, d, I64P, DP]
+        _lib.oracle_scan_ex.argtypes = [i, PP, PP, PP, PP, I64P, i, i, d, i, i, i, i, i, i, i64, d]
         for f in ("oracle_for_each", "oracle_reduce", "oracle_scan", "oracle_reduce_grad"):
             getattr(_lib, f).restype = i
     return _lib
@@ -145,3 +148,48 @@ def reduce_grad(in0, in1, in_dtype, op, g, which, mode=CONCAT, alpha=0.0):
                                     in_dtype, op, float(alpha), mode,
                                     g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), which))
     return outs
+
+
+def _init_args(in_dtype, init):
+    """(has_init, init_i, init_f) for the C calls; init None = the
+    operator's identity."""
+    if init is None:
+        return 0, 0, 0.0
+    if in_dtype == I32:
+        return 1, int(init), 0.0
+    return 1, 0, float(init)
+
+
+def reduce_ex(in0, in1, in_dtype, op, combine, mode=CONCAT, init=None, alpha=0.0):
+    """Per-result reduce with operator `combine` (SUM, MAX, MIN): int64 for
+    I32 inputs, binary64 otherwise."""
+    in0 = _prep(in0, in_dtype)
+    in1 = _prep(in1, in_dtype) if in1 is not None else None
+    nres = len(in0) if mode == BATCH else 1
+    has, ii, ff = _init_args(in_dtype, init)
+    ri = np.zeros(max(1, nres), dtype=np.int64)
+    rf = np.zeros(max(1, nres), dtype=np.float64)
+    _check(lib().oracle_reduce_ex(len(in0), _ptrs(in0), _ptrs(in1), _lengths(in0), in_dtype, op, float(alpha),
+                                  mode, combine, has, ii, ff,
+                                  ri.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  rf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return (ri if in_dtype == I32 else rf)[:nres]
+
+
+def scan_ex(in0, in1, in_dtype, op, combine, mode=CONCAT, reverse=False, exclusive=False, init=None,
+            out_dtype=None, alpha=0.0, want_abs=False):
+    """Per-segment outputs of the scan with operator `combine`, optional
+    init and exclusive form (and, for floating sums with want_abs, the
+    running sums of |v| including |init|)."""
+    in0 = _prep(in0, in_dtype)
+    in1 = _prep(in1, in_dtype) if in1 is not None else None
+    if out_dtype is None:
+        out_dtype = I64 if in_dtype == I32 else F64
+    has, ii, ff = _init_args(in_dtype, init)
+    outs = [np.empty(a.shape[0], dtype=_NP_DTYPE[out_dtype]) for a in in0]
+    absp = [np.empty(a.shape[0], dtype=np.float64) for a in in0] if want_abs else None
+    _check(lib().oracle_scan_ex(len(in0), _ptrs(in0), _ptrs(in1), _ptrs(outs), _ptrs(absp), _lengths(in0),
+                                in_dtype, op, float(alpha), mode, int(bool(reverse)), out_dtype, combine,
+                                int(bool(exclusive)), has, ii, ff))
+    return (outs, absp) if want_abs else outs
+

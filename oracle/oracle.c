@@ -393,4 +393,186 @@ int oracle_reduce_grad(int m, const void* const* in0, const void* const* in1,
     return OR_OK;
 }
 
+/* ---- generic reduce and scan (section 4.3) -------------------------------- */
+
+/*
+ * The paper's reduce and scan take any commutative binary operator (the
+ * footnote to section 4.3, "reduce"; its listings show +), reduce takes an
+ * initial value (Algorithm 3), and exclusive_scan is built like
+ * inclusive_scan (end of section 4.3, "inclusive_scan"). combine: 0 = sum,
+ * 1 = max, 2 = min.
+ *
+ * Readings:
+ *  - sum: as oracle_reduce / oracle_scan (exact view values, Neumaier
+ *    binary64), started from init instead of 0.
+ *  - max / min compare the view values as for_each would store them
+ *    (binary32 arithmetic with one rounding per operation for F32 and BF16
+ *    inputs, binary64 for F64, exact int64 for I32). Rounding is monotone,
+ *    so this is also the rounding of the exact maximum for identity, square
+ *    and mul views. NaN values are ignored (fmax / fmin) unless all are NaN.
+ *  - Without an initial value the identity of the operator is used:
+ *    0, -inf / INT64_MIN (max), +inf / INT64_MAX (min).
+ *  - exclusive: element i receives init combined with the elements strictly
+ *    before it (after it, in reverse); the first receives init.
+ */
+enum { OR_SUM = 0, OR_MAX = 1, OR_MIN = 2 };
+
+static double view_stored_fp(const void* in0, const void* in1, int64_t j, int dtype, int op, double alpha)
+{
+    if (dtype == OR_F64) {
+        double x = ((const double*)in0)[j];
+        switch (op) {
+        case OR_IDENTITY: return x;
+        case OR_SQUARE: return x * x;
+        case OR_MUL: return x * ((const double*)in1)[j];
+        default: { double t = alpha * ((const double*)in1)[j]; return x + t; }
+        }
+    }
+    float x = load_f32(in0, j, dtype);
+    switch (op) {
+    case OR_IDENTITY: return x;
+    case OR_SQUARE: { float r = x * x; return r; }
+    case OR_MUL: { float r = x * load_f32(in1, j, dtype); return r; }
+    default: { float t = (float)alpha * load_f32(in1, j, dtype); float r = x + t; return r; }
+    }
+}
+
+static double comb_fp(int combine, double a, double b)
+{
+    return combine == OR_MAX ? fmax(a, b) : fmin(a, b);
+}
+
+static int64_t comb_int(int combine, int64_t a, int64_t b)
+{
+    if (combine == OR_MAX)
+        return a > b ? a : b;
+    return a < b ? a : b;
+}
+
+/*
+ * Results as oracle_reduce (int64 for I32 inputs, binary64 otherwise), with
+ * the operator `combine` and, when has_init is 0, its identity as init.
+ */
+int oracle_reduce_ex(int m, const void* const* in0, const void* const* in1,
+                     const int64_t* len, int in_dtype, int op, double alpha, int mode,
+                     int combine, int has_init, int64_t init_i, double init_f,
+                     int64_t* result_i64, double* result_f64)
+{
+    if (combine == OR_SUM)
+        return oracle_reduce(m, in0, in1, len, in_dtype, op, alpha, mode,
+                             has_init ? init_i : 0, has_init ? init_f : 0.0,
+                             result_i64, result_f64, 0);
+    int rc = check_common(m, in0, in1, len, op);
+    if (rc != OR_OK || (mode != OR_CONCAT && mode != OR_BATCH) || (combine != OR_MAX && combine != OR_MIN))
+        return OR_EBADARG;
+    int is_int = (in_dtype == OR_I32);
+    if ((is_int && result_i64 == 0) || (!is_int && result_f64 == 0))
+        return OR_EBADARG;
+    if (!is_int && in_dtype != OR_F32 && in_dtype != OR_BF16 && in_dtype != OR_F64)
+        return OR_EBADARG;
+    int64_t i0 = has_init ? init_i : (combine == OR_MAX ? INT64_MIN : INT64_MAX);
+    double f0 = has_init ? init_f : (combine == OR_MAX ? -INFINITY : INFINITY);
+    int64_t ia = i0;
+    double fa = f0;
+    for (int k = 0; k < m; ++k) {
+        if (mode == OR_BATCH) {
+            ia = i0;
+            fa = f0;
+        }
+        const void* b = in1 ? in1[k] : 0;
+        for (int64_t j = 0; j < len[k]; ++j) {
+            if (is_int)
+                ia = comb_int(combine, ia, view_int(in0[k], b, j, op, (int64_t)alpha));
+            else
+                fa = comb_fp(combine, fa, view_stored_fp(in0[k], b, j, in_dtype, op, alpha));
+        }
+        if (mode == OR_BATCH) {
+            if (is_int)
+                result_i64[k] = ia;
+            else
+                result_f64[k] = fa;
+        }
+    }
+    if (mode == OR_CONCAT) {
+        if (is_int)
+            result_i64[0] = ia;
+        else
+            result_f64[0] = fa;
+    }
+    return OR_OK;
+}
+
+/*
+ * Outputs as oracle_scan (I32 input: int64 or int32-wrapped; floating
+ * input: binary64), with the operator `combine`, an optional initial value,
+ * and exclusive = 1 for the exclusive scan. abs_prefix (sum only, optional)
+ * receives the running sum of |v| including |init|, the scale of the
+ * rounding error.
+ */
+int oracle_scan_ex(int m, const void* const* in0, const void* const* in1,
+                   void* const* out, double* const* abs_prefix, const int64_t* len,
+                   int in_dtype, int op, double alpha, int mode, int reverse, int out_dtype,
+                   int combine, int exclusive, int has_init, int64_t init_i, double init_f)
+{
+    int rc = check_common(m, in0, in1, len, op);
+    if (rc != OR_OK || (mode != OR_CONCAT && mode != OR_BATCH))
+        return OR_EBADARG;
+    if (combine != OR_SUM && combine != OR_MAX && combine != OR_MIN)
+        return OR_EBADARG;
+    int is_int = (in_dtype == OR_I32);
+    if (is_int && out_dtype != OR_I64 && out_dtype != OR_I32)
+        return OR_EBADARG;
+    if (!is_int && (in_dtype != OR_F32 && in_dtype != OR_BF16 && in_dtype != OR_F64))
+        return OR_EBADARG;
+    if (!is_int && out_dtype != OR_F64)
+        return OR_EBADARG;
+    if (combine != OR_SUM && abs_prefix)
+        return OR_EBADARG;
+    int64_t i0 = has_init ? init_i : (combine == OR_SUM ? 0 : combine == OR_MAX ? INT64_MIN : INT64_MAX);
+    double f0 = has_init ? init_f : (combine == OR_SUM ? 0.0 : combine == OR_MAX ? -INFINITY : INFINITY);
+
+    int64_t iacc = i0;
+    double facc_m = f0;                 /* max / min */
+    nsum facc = { f0, 0.0 };            /* sum */
+    nsum mag = { fabs(f0), 0.0 };
+    for (int kk = 0; kk < m; ++kk) {
+        int k = reverse ? (m - 1 - kk) : kk;
+        if (mode == OR_BATCH) {
+            iacc = i0;
+            facc_m = f0;
+            facc.s = f0;
+            facc.c = 0.0;
+            mag.s = fabs(f0);
+            mag.c = 0.0;
+        }
+        const void* b = in1 ? in1[k] : 0;
+        for (int64_t jj = 0; jj < len[k]; ++jj) {
+            int64_t j = reverse ? (len[k] - 1 - jj) : jj;
+            if (is_int) {
+                int64_t before = iacc;
+                int64_t v = view_int(in0[k], b, j, op, (int64_t)alpha);
+                iacc = combine == OR_SUM ? iacc + v : comb_int(combine, iacc, v);
+                int64_t y = exclusive ? before : iacc;
+                if (out_dtype == OR_I64)
+                    ((int64_t*)out[k])[j] = y;
+                else
+                    ((int32_t*)out[k])[j] = (int32_t)(uint32_t)(uint64_t)y;
+            } else if (combine == OR_SUM) {
+                double before = nsum_value(&facc), mbefore = nsum_value(&mag);
+                double v = view_fp(in0[k], b, j, in_dtype, op, alpha);
+                nsum_add(&facc, v);
+                nsum_add(&mag, fabs(v));
+                ((double*)out[k])[j] = exclusive ? before : nsum_value(&facc);
+                if (abs_prefix)
+                    abs_prefix[k][j] = exclusive ? mbefore : nsum_value(&mag);
+            } else {
+                double before = facc_m;
+                facc_m = comb_fp(combine, facc_m, view_stored_fp(in0[k], b, j, in_dtype, op, alpha));
+                ((double*)out[k])[j] = exclusive ? before : facc_m;
+            }
+        }
+    }
+    return OR_OK;
+}
+
 int oracle_abi_version(void) { return 1; }

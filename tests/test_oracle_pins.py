@@ -432,3 +432,112 @@ def test_oracle_rejects_bad_arguments():
         O.reduce([np.ones(3, np.float32)], None, O.F32, O.MUL)   # arity 2 without a second input
     with pytest.raises(TypeError):
         O.scan([np.ones(3, np.float64)], None, O.F32, O.IDENTITY)
+
+
+# --- generic operators, init and exclusive scans (section 4.3) -------------------
+
+def test_exclusive_sum_scan_of_ones_with_init_is_shifted_iota():
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        lens = _rand_segmentation(int(rng.integers(0, 60)), rng)
+        n = sum(lens)
+        ones = I.split(np.ones(n, dtype=np.int32), lens)
+        c = int(rng.integers(-1000, 1000))
+        ex = np.concatenate(O.scan_ex(ones, None, O.I32, O.IDENTITY, O.SUM, exclusive=True, init=c)) if n else []
+        inc = np.concatenate(O.scan_ex(ones, None, O.I32, O.IDENTITY, O.SUM, init=c)) if n else []
+        assert list(ex) == [c + i for i in range(n)]
+        assert list(inc) == [c + i + 1 for i in range(n)]
+        # BATCH: every range restarts from init
+        outs = O.scan_ex(ones, None, O.I32, O.IDENTITY, O.SUM, mode=O.BATCH, exclusive=True, init=c)
+        for o, L in zip(outs, lens):
+            assert list(o) == [c + j for j in range(L)]
+        # floating: the same closed form, exactly
+        fo = I.split(np.ones(n, dtype=np.float32), lens)
+        fex = np.concatenate(O.scan_ex(fo, None, O.F32, O.IDENTITY, O.SUM, exclusive=True, init=c + 0.5)) if n else []
+        assert list(fex) == [c + 0.5 + i for i in range(n)]
+
+
+def test_exclusive_is_inclusive_shifted_for_every_operator_and_direction():
+    rng = np.random.default_rng(12)
+    for trial in range(30):
+        lens = _rand_segmentation(int(rng.integers(1, 50)), rng)
+        n = sum(lens)
+        k = (rng.integers(-100, 101, size=n)).astype(np.int32)
+        segs = I.split(k, lens)
+        for comb, mode, rev in itertools.product((O.SUM, O.MAX, O.MIN), (O.CONCAT, O.BATCH), (False, True)):
+            init = int(rng.integers(-50, 50)) if trial % 2 else None
+            inc = O.scan_ex(segs, None, O.I32, O.IDENTITY, comb, mode=mode, reverse=rev, init=init)
+            exc = O.scan_ex(segs, None, O.I32, O.IDENTITY, comb, mode=mode, reverse=rev, exclusive=True, init=init)
+            ident = {O.SUM: 0, O.MAX: np.iinfo(np.int64).min, O.MIN: np.iinfo(np.int64).max}[comb]
+            start = ident if init is None else init
+            # flatten in processing order (reverse: last element first)
+            if mode == O.BATCH:
+                groups = [(i, e) for i, e in zip(inc, exc)]
+            else:
+                groups = [(np.concatenate(inc), np.concatenate(exc))]
+            for gi, ge in groups:
+                if rev:
+                    gi, ge = gi[::-1], ge[::-1]
+                if len(gi):
+                    assert ge[0] == start
+                    assert np.array_equal(ge[1:], gi[:-1])
+
+
+def test_max_min_scans_and_reduces_are_numpy_accumulates():
+    """max / min of the values for_each would store: numpy's fmax / fmin
+    accumulate over the float32 view values (NaN ignored), in both
+    directions, per range in BATCH mode."""
+    rng = np.random.default_rng(13)
+    for trial in range(25):
+        lens = _rand_segmentation(int(rng.integers(1, 80)), rng)
+        n = sum(lens)
+        x = rng.standard_normal(n).astype(np.float32)
+        y = rng.standard_normal(n).astype(np.float32)
+        if n > 3 and trial % 3 == 0:
+            x[int(rng.integers(0, n))] = np.nan
+        for name, op in OPS.items():
+            a = np.float32(0.375)
+            v = {"identity": x, "square": x * x, "mul": x * y, "axpy": x + a * y}[name].astype(np.float32)
+            for comb, acc in ((O.MAX, np.fmax), (O.MIN, np.fmin)):
+                got = np.concatenate(O.scan_ex(I.split(x, lens), I.split(y, lens), O.F32, op, comb, alpha=0.375))
+                assert np.array_equal(got, acc.accumulate(v.astype(np.float64)), equal_nan=True)
+                rgot = np.concatenate(O.scan_ex(I.split(x, lens), I.split(y, lens), O.F32, op, comb, reverse=True,
+                                                alpha=0.375))
+                assert np.array_equal(rgot, acc.accumulate(v[::-1].astype(np.float64))[::-1], equal_nan=True)
+                red = O.reduce_ex(I.split(x, lens), I.split(y, lens), O.F32, op, comb, alpha=0.375)
+                assert np.array_equal(red, [acc.reduce(v.astype(np.float64))], equal_nan=True)
+                bred = O.reduce_ex(I.split(x, lens), I.split(y, lens), O.F32, op, comb, mode=O.BATCH, alpha=0.375)
+                want = [acc.reduce(p.astype(np.float64)) if len(p) else (-np.inf if comb == O.MAX else np.inf)
+                        for p in I.split(v, lens)]
+                assert np.array_equal(bred, want, equal_nan=True)
+
+
+def test_max_min_closed_forms_and_init():
+    n = 1000
+    iota = np.arange(n, dtype=np.int32)
+    lens = [100, 0, 400, 500]
+    assert list(np.concatenate(O.scan_ex(I.split(iota, lens), None, O.I32, O.IDENTITY, O.MAX))) == list(range(n))
+    assert set(np.concatenate(O.scan_ex(I.split(iota[::-1].copy(), lens), None, O.I32, O.IDENTITY, O.MAX))) == {n - 1}
+    assert O.reduce_ex(I.split(iota, lens), None, O.I32, O.SQUARE, O.MAX)[0] == (n - 1) ** 2
+    assert O.reduce_ex(I.split(iota, lens), None, O.I32, O.IDENTITY, O.MIN, init=-7)[0] == -7
+    assert O.reduce_ex(I.split(iota, lens), None, O.I32, O.IDENTITY, O.MAX, init=5000)[0] == 5000
+    # empty ranges give init, or the identity without one
+    e = [np.zeros(0, dtype=np.float32)]
+    assert O.reduce_ex(e, None, O.F32, O.IDENTITY, O.MAX)[0] == -np.inf
+    assert O.reduce_ex(e, None, O.F32, O.IDENTITY, O.MIN, init=2.5)[0] == 2.5
+    # int32 output of a max scan wraps like the sum scan's
+    big = [np.array([5], dtype=np.int32)]
+    assert O.scan_ex(big, None, O.I32, O.IDENTITY, O.MAX, init=2 ** 33 + 9, out_dtype=O.I32)[0][0] == 9
+
+
+def test_sum_with_init_matches_fsum():
+    rng = np.random.default_rng(14)
+    x = (rng.standard_normal(5000) * np.exp(rng.uniform(-20, 20, 5000))).astype(np.float32)
+    lens = [1000, 2500, 1500]
+    init = 1.2345e7
+    r = O.reduce_ex(I.split(x, lens), None, O.F32, O.IDENTITY, O.SUM, init=init)[0]
+    assert r == math.fsum([init] + [float(v) for v in x])
+    ex = np.concatenate(O.scan_ex(I.split(x, lens), None, O.F32, O.IDENTITY, O.SUM, exclusive=True, init=init))
+    for i in (0, 1, 17, 2499, 4999):
+        want = math.fsum([init] + [float(v) for v in x[:i]])
+        assert abs(ex[i] - want) <= 2 * U64 * (abs(init) + float(np.abs(x[:i].astype(np.float64)).sum()))
