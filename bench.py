@@ -218,7 +218,19 @@ def configs_report(reps: int) -> int:
     for fl, nm in ((0, "binary64 carries"), (B.DR_SCAN_CARRY_F32, "binary32 carries")):
         report("C3 scan", f"f32 2^28, {nm}", 8 * x.numel(), lambda: B.dr_inclusive_scan(
             tab, B.make_view("identity", B.DR_F32), B.DR_F32, fl, workspace=ws, host_check=False))
-    del x, out, tab
+    # the generic operators on the same data (section 4.3): exclusive sum with
+    # an initial value, running max, and max / min reductions
+    vid = B.make_view("identity", B.DR_F32)
+    report("C3 scan", "f32 2^28, exclusive sum with init", 8 * x.numel(), lambda: B.dr_scan(
+        tab, vid, B.DR_F32, B.DR_COMBINE_SUM, B.DR_SCAN_EXCLUSIVE, 1.5, workspace=ws, host_check=False))
+    report("C3 scan", "f32 2^28, inclusive max", 8 * x.numel(), lambda: B.dr_scan(
+        tab, vid, B.DR_F32, B.DR_COMBINE_MAX, 0, None, workspace=ws, host_check=False))
+    tx = B.segments([pieces(x, L)])
+    rm = torch.zeros(1, dtype=torch.float64, device=dev)
+    for cm, nm in ((B.DR_COMBINE_MAX, "max"), (B.DR_COMBINE_MIN, "min")):
+        report("C3 scan", f"f32 2^28, reduce {nm}", 4 * x.numel(), lambda: B.dr_reduce(
+            tx, vid, cm, 0, None, rm, workspace=ws, host_check=False))
+    del x, out, tab, tx
 
     # C4 precision: 2^29 mixture, binary32 and bfloat16, plain vs compensated
     t = I.precision()

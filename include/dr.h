@@ -301,6 +301,55 @@ dr_status dr_broadcast_mul(const dr_table* table, const dr_view* view, const dou
                            int32_t n_grads, void* workspace, size_t ws_bytes,
                            const dr_tuning* tuning, void* stream);
 
+/* ---- Generic operators (section 4.3) ----------------------------------------
+ * The paper's reduce and scan take any commutative binary operator (its
+ * listings show +), reduce takes an initial value, and exclusive_scan is
+ * built like inclusive_scan. */
+
+/* Combine operators. Max / min compare the view values as dr_for_each
+ * would store them (binary32 arithmetic with one rounding per operation for
+ * F32 and BF16 inputs, binary64 for F64, exact int64 for I32); the results
+ * are exact. NaN values are ignored (IEEE maxNum / minNum) unless every
+ * value is NaN. */
+typedef enum dr_combine { DR_COMBINE_SUM = 0, DR_COMBINE_MAX = 1, DR_COMBINE_MIN = 2 } dr_combine;
+
+/* dr_scan flag (with DR_SCAN_REVERSE, DR_SCAN_CARRY_F32): exclusive scan. */
+enum { DR_SCAN_EXCLUSIVE = 4 };
+
+/*
+ * reduce with an operator (section 4.3, "reduce"; Algorithm 3): R = init
+ * combined with every view value (CONCAT), or R_k per segment (BATCH).
+ * `init` is a host pointer (int64_t for I32 inputs, double otherwise) or
+ * NULL for the operator's identity (0, -inf / INT64_MIN for max,
+ * +inf / INT64_MAX for min); an empty range gives it. DR_COMBINE_SUM is
+ * dr_transform_reduce (`acc` as there); for max / min `acc` is ignored and
+ * every op and input dtype is supported at the default tile (16 items per
+ * thread). Results, workspace and tuning as dr_transform_reduce.
+ */
+dr_status dr_reduce(const dr_table* table, const dr_view* view, int32_t combine, int32_t acc,
+                    const void* init, void* result, void* workspace, size_t ws_bytes,
+                    const dr_tuning* tuning, void* stream);
+
+/*
+ * scan with an operator, an initial value and the exclusive form (section
+ * 4.3, "inclusive_scan" and the exclusive_scan built like it): element i
+ * of the range receives init combined with the view values up to and
+ * including i (inclusive), or strictly before i (DR_SCAN_EXCLUSIVE; the first
+ * element receives init); after i instead of before it with
+ * DR_SCAN_REVERSE; per segment in BATCH mode. `init` is a host int64_t (I32
+ * inputs) or double, or NULL for the identity. The initial value enters the
+ * outputs only (binary64 for floating inputs, rounded once with the
+ * element's value into the output type).
+ * DR_COMBINE_SUM: the dtypes, ops, flags and forms of dr_inclusive_scan;
+ * DR_COMBINE_MAX / MIN: the identity view, every dtype pair of
+ * dr_inclusive_scan, the default (reduce-then-scan) form at 16 items per
+ * thread; DR_SCAN_CARRY_F32 and DR_TUNE_TILE_PER_BLOCK are rejected
+ * (DR_ERR_UNSUPPORTED).
+ */
+dr_status dr_scan(const dr_table* table, const dr_view* view, int32_t out_dtype, int32_t combine,
+                  uint32_t flags, const void* init, void* workspace, size_t ws_bytes,
+                  const dr_tuning* tuning, void* stream);
+
 /* ---- Segment algebra (host side; section 4.4) ------------------------------
  * Views that change which elements or which segment boundaries a call sees.
  * They only compute new segment lists on the host; the kernels above then

@@ -26,7 +26,9 @@ DR_I32, DR_F32, DR_BF16, DR_F64, DR_I64 = 0, 1, 2, 3, 4
 DR_OP_IDENTITY, DR_OP_SQUARE, DR_OP_MUL, DR_OP_AXPY = 0, 1, 2, 3
 DR_ACC_PLAIN, DR_ACC_COMPENSATED = 0, 1
 DR_MODE_CONCAT, DR_MODE_BATCH = 0, 1
-DR_SCAN_REVERSE, DR_SCAN_CARRY_F32 = 1, 2
+DR_SCAN_REVERSE, DR_SCAN_CARRY_F32, DR_SCAN_EXCLUSIVE = 1, 2, 4
+DR_COMBINE_SUM, DR_COMBINE_MAX, DR_COMBINE_MIN = 0, 1, 2
+COMBINES = {"sum": DR_COMBINE_SUM, "max": DR_COMBINE_MAX, "min": DR_COMBINE_MIN}
 DR_ALGO_FOR_EACH, DR_ALGO_REDUCE, DR_ALGO_SCAN, DR_ALGO_SCAN_REDUCE, DR_ALGO_BROADCAST_MUL = 0, 1, 2, 3, 4
 DR_SMALL_TABLE = 64
 DR_MAX_ARITY = 4
@@ -78,7 +80,7 @@ assert ctypes.sizeof(dr_view) == 24
 EXPORTS = ["dr_abi_version", "dr_status_string", "dr_last_error", "dr_tuning_supported",
            "dr_workspace_bytes", "dr_workspace_init", "dr_plan", "dr_for_each",
            "dr_transform_reduce", "dr_inclusive_scan", "dr_scan_reduce", "dr_broadcast_mul",
-           "dr_device_status", "dr_trim_segments", "dr_zip_segments"]
+           "dr_device_status", "dr_trim_segments", "dr_zip_segments", "dr_reduce", "dr_scan"]
 
 _lib = None
 
@@ -114,6 +116,8 @@ def lib() -> ctypes.CDLL:
     L.dr_scan_reduce.argtypes = [TP, VP, VP, i32, P, P, u32, P, S, UP, P]
     L.dr_broadcast_mul.argtypes = [TP, VP, P, i32, P, S, UP, P]
     L.dr_device_status.argtypes = [P, ctypes.POINTER(u32), P]
+    L.dr_reduce.argtypes = [TP, VP, i32, i32, P, P, P, S, UP, P]
+    L.dr_scan.argtypes = [TP, VP, i32, i32, u32, P, P, S, UP, P]
     RP, I64P = ctypes.POINTER(dr_range), ctypes.POINTER(i64)
     L.dr_trim_segments.argtypes = [RP, i64, i64, ctypes.POINTER(dr_span), i64, I64P]
     L.dr_zip_segments.argtypes = [RP, i32, RP, i32, ctypes.POINTER(dr_segment), i64, I64P, I64P]
@@ -307,6 +311,35 @@ def dr_transform_reduce(table: Table, view: dr_view, acc: int, init, result: tor
     check(lib().dr_transform_reduce(ctypes.byref(c), ctypes.byref(view), acc, ctypes.byref(init_c),
                                     result.data_ptr() if result.numel() else None, workspace.ptr,
                                     workspace.nbytes, _tp(tuning), _stream(table.device)))
+
+
+def _init_ref(view: dr_view, init):
+    """ctypes value for an initial value (None = the operator's identity)."""
+    if init is None:
+        return None, None
+    v = ctypes.c_int64(int(init)) if view.in_dtype == DR_I32 else ctypes.c_double(float(init))
+    return v, ctypes.byref(v)
+
+
+def dr_reduce(table: Table, view: dr_view, combine: int, acc: int, init, result: torch.Tensor,
+              workspace: Workspace | None = None, tuning: dr_tuning | None = None, host_check: bool = True) -> None:
+    workspace = workspace or default_workspace(table.device)
+    workspace.for_call(DR_ALGO_REDUCE, table, view, tuning)
+    c = table.c_table(host_check)
+    keep, ref = _init_ref(view, init)
+    check(lib().dr_reduce(ctypes.byref(c), ctypes.byref(view), combine, acc, ref,
+                          result.data_ptr() if result.numel() else None, workspace.ptr, workspace.nbytes,
+                          _tp(tuning), _stream(table.device)))
+
+
+def dr_scan(table: Table, view: dr_view, out_dtype: int, combine: int = DR_COMBINE_SUM, flags: int = 0, init=None,
+            workspace: Workspace | None = None, tuning: dr_tuning | None = None, host_check: bool = True) -> None:
+    workspace = workspace or default_workspace(table.device)
+    workspace.for_call(DR_ALGO_SCAN, table, view, tuning)
+    c = table.c_table(host_check)
+    keep, ref = _init_ref(view, init)
+    check(lib().dr_scan(ctypes.byref(c), ctypes.byref(view), out_dtype, combine, flags, ref, workspace.ptr,
+                        workspace.nbytes, _tp(tuning), _stream(table.device)))
 
 
 def dr_inclusive_scan(table: Table, view: dr_view, out_dtype: int, flags: int = 0,

@@ -431,6 +431,86 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
     return launch(fn, p, stream, "inclusive_scan launch");
 }
 
+dr_status dr_reduce(const dr_table* table, const dr_view* view, int32_t combine, int32_t acc, const void* init,
+                    void* result, void* ws, size_t ws_bytes, const dr_tuning* tuning, void* stream) {
+    if (combine == DR_COMBINE_SUM) {
+        const int64_t zero_i = 0;
+        const double zero_f = 0.0;
+        const void* iv = init ? init : (view && view->in_dtype == DR_I32 ? (const void*)&zero_i : (const void*)&zero_f);
+        return dr_transform_reduce(table, view, acc, iv, result, ws, ws_bytes, tuning, stream);
+    }
+    if (combine != DR_COMBINE_MAX && combine != DR_COMBINE_MIN)
+        return fail(DR_ERR_INVALID_ARG, "unknown combine %d", combine);
+    dr_status s = check_view(view, true);
+    if (s) return s;
+    if (!result && !(table && table->mode == DR_MODE_BATCH && table->n_segments == 0))
+        return fail(DR_ERR_INVALID_ARG, "result is NULL");
+    if (tuning && tuning->items_per_thread != 0 && tuning->items_per_thread != 16)
+        return fail(DR_ERR_UNSUPPORTED, "max / min reductions are built for 16 items per thread");
+    Prepared p;
+    int items;
+    s = prepare(table, DR_ALGO_REDUCE, view->in_dtype, 0, view->arity, 0, tuning, ws, ws_bytes, true, false, p,
+                items);
+    if (s) return s;
+    LaunchFn fn = find_reduce_minmax(view->in_dtype, view->op);
+    if (!fn) return fail(DR_ERR_UNSUPPORTED, "max / min reduce kernel not built for this combination");
+    const bool mn = combine == DR_COMBINE_MIN;
+    p.a.alpha = view->alpha;
+    p.a.result = result;
+    if (mn) p.a.flags |= kFlagMin;
+    if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) p.a.flags |= kFlagTilePerBlock;
+    if (view->in_dtype == DR_I32)
+        p.a.init_i = init ? *(const int64_t*)init : (mn ? INT64_MAX : INT64_MIN);
+    else
+        p.a.init_f = init ? *(const double*)init : (mn ? HUGE_VAL : -HUGE_VAL);
+    return launch(fn, p, stream, "reduce launch");
+}
+
+dr_status dr_scan(const dr_table* table, const dr_view* view, int32_t out_dtype, int32_t combine, uint32_t flags,
+                  const void* init, void* ws, size_t ws_bytes, const dr_tuning* tuning, void* stream) {
+    if (combine != DR_COMBINE_SUM && combine != DR_COMBINE_MAX && combine != DR_COMBINE_MIN)
+        return fail(DR_ERR_INVALID_ARG, "unknown combine %d", combine);
+    dr_status s = check_view(view, true);
+    if (s) return s;
+    const int in = view->in_dtype;
+    const bool okpair = (in == DR_I32 && (out_dtype == DR_I64 || out_dtype == DR_I32)) ||
+                        (in == DR_F32 && out_dtype == DR_F32) || (in == DR_BF16 && out_dtype == DR_F32) ||
+                        (in == DR_F64 && out_dtype == DR_F64);
+    if (!okpair) return fail(DR_ERR_UNSUPPORTED, "scan %d -> %d is not supported", in, (int)out_dtype);
+    if (flags & ~(uint32_t)(DR_SCAN_REVERSE | DR_SCAN_CARRY_F32 | DR_SCAN_EXCLUSIVE))
+        return fail(DR_ERR_INVALID_ARG, "unknown scan flags 0x%x", flags);
+    if ((flags & DR_SCAN_CARRY_F32) && in != DR_F32 && in != DR_BF16)
+        return fail(DR_ERR_INVALID_ARG, "DR_SCAN_CARRY_F32 applies to binary32/bfloat16 inputs only");
+    const bool mm = combine != DR_COMBINE_SUM;
+    if (mm) {
+        if (view->op != DR_OP_IDENTITY)
+            return fail(DR_ERR_UNSUPPORTED, "max / min scans are built for the identity view");
+        if (flags & DR_SCAN_CARRY_F32) return fail(DR_ERR_UNSUPPORTED, "DR_SCAN_CARRY_F32 applies to sums");
+        if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK))
+            return fail(DR_ERR_UNSUPPORTED, "max / min scans run in the reduce-then-scan form only");
+        if (tuning && tuning->items_per_thread != 0 && tuning->items_per_thread != 16)
+            return fail(DR_ERR_UNSUPPORTED, "max / min scans are built for 16 items per thread");
+    }
+    Prepared p;
+    int items;
+    s = prepare(table, DR_ALGO_SCAN, in, out_dtype, view->arity, 1, tuning, ws, ws_bytes, true,
+                view->op == DR_OP_IDENTITY, p, items);
+    if (s) return s;
+    LaunchFn fn = mm ? find_scan_minmax(in, out_dtype)
+                     : find_scan(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items);
+    if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
+    p.a.alpha = view->alpha;
+    p.a.flags = flags;
+    if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) p.a.flags |= kFlagTilePerBlock;
+    if (combine == DR_COMBINE_MIN) p.a.flags |= kFlagMin;
+    if (init) {
+        p.a.flags |= kFlagHasInit;
+        if (in == DR_I32) p.a.init_i = *(const int64_t*)init;
+        else p.a.init_f = *(const double*)init;
+    }
+    return launch(fn, p, stream, "scan launch");
+}
+
 dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view, const dr_view* reduce_view,
                          int32_t acc, const void* init, void* result, uint32_t flags, void* ws, size_t ws_bytes,
                          const dr_tuning* tuning, void* stream) {

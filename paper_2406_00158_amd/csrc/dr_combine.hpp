@@ -20,12 +20,14 @@
 
 namespace dr {
 
-template <class P>
+// result[unit] = init combined with `sum` (the unit's combined partials).
+template <class P, int CMB = kCmbSum>
 __device__ __forceinline__ void write_result(const LaunchArgs& a, int64_t unit, P sum) {
+    const bool mn = (a.flags & kFlagMin) != 0;
     if constexpr (!std::is_floating_point<P>::value) {
-        ((int64_t*)a.result)[unit] = a.init_i + (int64_t)sum;
+        ((int64_t*)a.result)[unit] = cmb_op<CMB>(a.init_i, (int64_t)sum, mn);
     } else {
-        ((double*)a.result)[unit] = a.init_f + (double)sum;
+        ((double*)a.result)[unit] = cmb_op<CMB>(a.init_f, (double)sum, mn);
     }
 }
 
@@ -49,9 +51,10 @@ __device__ __forceinline__ P wait_tagged(const LaunchArgs& a, const uint64_t* w,
 // Results of the empty BATCH segments that follow segment k (k = -1: the
 // leading ones) are `init`: written by the workgroup of the first tile of
 // the preceding non-empty segment. Thread 0 only.
-template <class P>
+template <class P, int CMB = kCmbSum>
 __device__ __forceinline__ void fill_empty_after(const LaunchArgs& a, int64_t k) {
-    for (int64_t kk = k + 1; kk < a.m && a.rows[kk].length == 0; ++kk) write_result<P>(a, kk, (P)0);
+    const P id = cmb_id<CMB, P>((a.flags & kFlagMin) != 0);
+    for (int64_t kk = k + 1; kk < a.m && a.rows[kk].length == 0; ++kk) write_result<P, CMB>(a, kk, id);
 }
 
 // Member `idx` (0-based within its unit of `count` members, whose partial
@@ -59,9 +62,11 @@ __device__ __forceinline__ void fill_empty_after(const LaunchArgs& a, int64_t k)
 // `partial` (held by lane 0) and, if it completes its group or the unit,
 // combines. `slot0` is the unit's first group slot. Called by ONE whole wave
 // (the other waves of the workgroup need not wait for it).
-template <class P>
+template <class P, int CMB = kCmbSum>
 __device__ __forceinline__ void combine_member(const LaunchArgs& a, uint32_t tag, int64_t unit, int64_t base,
                                                int64_t idx, int64_t count, int64_t slot0, P partial) {
+    const bool mn = (a.flags & kFlagMin) != 0;
+    const P id = cmb_id<CMB, P>(mn);
     const int64_t gi = idx / kGroupTiles;
     const int64_t g0 = gi * kGroupTiles;
     const int64_t gn = (count - g0) < kGroupTiles ? (count - g0) : kGroupTiles;
@@ -73,7 +78,7 @@ __device__ __forceinline__ void combine_member(const LaunchArgs& a, uint32_t tag
     const int64_t TW = a.lay.tile_words, PW = a.lay.part_word;
     const int l = lane_id();
     if (count == 1) {   // the unit's only member: nothing to wait for or count
-        if (l == 0) write_result<P>(a, unit, partial);
+        if (l == 0) write_result<P, CMB>(a, unit, partial);
         return;
     }
 
@@ -84,11 +89,11 @@ __device__ __forceinline__ void combine_member(const LaunchArgs& a, uint32_t tag
     }
     if (!readlane(last_in_group, 0)) return;
     // the group is complete: sum its partials in member order
-    P v = (P)0;
+    P v = id;
     if (l < gn) v = wait_tagged<P>(a, tw + (base + g0 + l) * TW + PW, tag);
-    const P gsum = wave_sum(v);
+    const P gsum = wave_reduce_cmb<CMB>(v, mn);
     if (ngroups == 1) {
-        if (l == 0) write_result<P>(a, unit, gsum);
+        if (l == 0) write_result<P, CMB>(a, unit, gsum);
         return;
     }
     int last = 0;
@@ -97,29 +102,31 @@ __device__ __forceinline__ void combine_member(const LaunchArgs& a, uint32_t tag
         last = atomic_add32(ucnt + unit, 1u) == (uint32_t)(ngroups - 1);
     }
     if (!readlane(last, 0)) return;
-    P acc = (P)0;
-    for (int64_t g = l; g < ngroups; g += 64) acc += wait_tagged<P>(a, gpart + (slot0 + g) * 2, tag);
-    const P tot = wave_sum(acc);
-    if (l == 0) write_result<P>(a, unit, tot);
+    P acc = id;
+    for (int64_t g = l; g < ngroups; g += 64) acc = cmb_op<CMB>(acc, wait_tagged<P>(a, gpart + (slot0 + g) * 2, tag), mn);
+    const P tot = wave_reduce_cmb<CMB>(acc, mn);
+    if (l == 0) write_result<P, CMB>(a, unit, tot);
 }
 
 // BATCH: tile t of segment si publishes its partial; the segment's last
 // group writes result[k]. Group slots of segment k start at first/64 + k.
 // One whole wave.
-template <class P>
+template <class P, int CMB = kCmbSum>
 __device__ __forceinline__ void combine_tile_batch(const LaunchArgs& a, uint32_t tag, int64_t t,
                                                    const SegInfo& si, P partial) {
     if (lane_id() == 0 && t == si.first) {
-        if (t == 0) fill_empty_after<P>(a, -1);
-        fill_empty_after<P>(a, si.k);
+        if (t == 0) fill_empty_after<P, CMB>(a, -1);
+        fill_empty_after<P, CMB>(a, si.k);
     }
-    combine_member<P>(a, tag, si.k, si.first, t - si.first, si.ntiles, si.first / kGroupTiles + si.k, partial);
+    combine_member<P, CMB>(a, tag, si.k, si.first, t - si.first, si.ntiles, si.first / kGroupTiles + si.k,
+                           partial);
 }
 
 // BATCH launch with no tiles at all: every result is `init`.
-template <class P>
+template <class P, int CMB = kCmbSum>
 __device__ __forceinline__ void write_all_init(const LaunchArgs& a) {
-    for (int64_t k = 0; k < a.m; ++k) write_result<P>(a, k, (P)0);
+    const P id = cmb_id<CMB, P>((a.flags & kFlagMin) != 0);
+    for (int64_t k = 0; k < a.m; ++k) write_result<P, CMB>(a, k, id);
 }
 
 }  // namespace dr

@@ -7,6 +7,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <limits>
+#include <type_traits>
+
 #include "dr.h"
 #include "dr_internal.hpp"
 
@@ -133,6 +136,88 @@ __device__ __forceinline__ T wave_sum(T x) {
 }
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// ---------------------------------------------------------------------------
+// Combine operators of the generic algorithms
+// ---------------------------------------------------------------------------
+//
+// kCmbSum: +. kCmbMinMax: max, or min when `mn` (a launch-wide flag); NaN
+// operands are ignored (IEEE maxNum / minNum) unless both are NaN. Sums keep
+// their own code paths (compensation, carries); these helpers carry the
+// operator through the scan and combine structure.
+
+constexpr int kCmbSum = 0;
+constexpr int kCmbMinMax = 1;
+
+template <class T>
+__device__ __forceinline__ T mm_op(T a, T b, bool mn) {
+    if constexpr (sizeof(T) == 4 && std::is_floating_point<T>::value) {
+        return mn ? __builtin_fminf(a, b) : __builtin_fmaxf(a, b);
+    } else if constexpr (std::is_floating_point<T>::value) {
+        return mn ? __builtin_fmin(a, b) : __builtin_fmax(a, b);
+    } else {
+        return mn ? (a < b ? a : b) : (a > b ? a : b);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T mm_id(bool mn) {
+    if constexpr (std::is_floating_point<T>::value) return mn ? (T)__builtin_inf() : -(T)__builtin_inf();
+    else return mn ? std::numeric_limits<T>::max() : std::numeric_limits<T>::min();
+}
+
+template <int CMB, class T>
+__device__ __forceinline__ T cmb_op(T a, T b, bool mn) {
+    if constexpr (CMB == kCmbSum) return a + b;
+    else return mm_op(a, b, mn);
+}
+
+template <int CMB, class T>
+__device__ __forceinline__ T cmb_id(bool mn) {
+    if constexpr (CMB == kCmbSum) return (T)0;
+    else return mm_id<T>(mn);
+}
+
+// DPP move whose lanes without a source receive `old` instead of 0.
+template <int CTRL, int ROW_MASK, class T>
+__device__ __forceinline__ T dpp_move_or(T x, T old) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                 __builtin_bit_cast(int, x), CTRL, ROW_MASK,
+                                                                 0xf, false));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, x), o = __builtin_bit_cast(uint64_t, old);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u, CTRL,
+                                                                  ROW_MASK, 0xf, false);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32),
+                                                                  (int)(uint32_t)(u >> 32), CTRL, ROW_MASK,
+                                                                  0xf, false);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Inclusive scan over the wave with the operator (the sum uses the plain
+// DPP scan above).
+template <int CMB, class T>
+__device__ __forceinline__ T wave_incl_scan_cmb(T x, bool mn) {
+    if constexpr (CMB == kCmbSum) {
+        return wave_incl_scan(x);
+    } else {
+        const T id = mm_id<T>(mn);
+        x = mm_op(x, dpp_move_or<DPP_ROW_SHR1, 0xf>(x, id), mn);
+        x = mm_op(x, dpp_move_or<DPP_ROW_SHR2, 0xf>(x, id), mn);
+        x = mm_op(x, dpp_move_or<DPP_ROW_SHR4, 0xf>(x, id), mn);
+        x = mm_op(x, dpp_move_or<DPP_ROW_SHR8, 0xf>(x, id), mn);
+        x = mm_op(x, dpp_move_or<DPP_ROW_BCAST15, 0xa>(x, id), mn);
+        x = mm_op(x, dpp_move_or<DPP_ROW_BCAST31, 0xc>(x, id), mn);
+        return x;
+    }
+}
+
+template <int CMB, class T>
+__device__ __forceinline__ T wave_reduce_cmb(T x, bool mn) {
+    return readlane(wave_incl_scan_cmb<CMB>(x, mn), 63);
+}
 
 // ---------------------------------------------------------------------------
 // Error-free transformations (binary32)
@@ -535,6 +620,18 @@ __device__ __forceinline__ void load_slots(vec<DT> (&x)[SLOTS], const void* base
             }
         }
     }
+}
+
+// Whether element e (memory order) of slot s of lane l of wave w lies
+// inside the segment; the loads fill the others with 0, which only a sum may
+// combine.
+template <int V, int SLOTS>
+__device__ __forceinline__ bool elem_in(const SegInfo& si, int64_t u0, int w, int l, int s, int e, bool rev) {
+    constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+    const int64_t p = (int64_t)(w * SLOTS + s) * 64 + l;
+    const int64_t q = rev ? (NV - 1 - p) : p;
+    const int64_t j = u0 + q * V - si.shift + e;
+    return j >= 0 && j < si.n;
 }
 
 // Store the V outputs of slot s (given in memory order). `full` is

@@ -90,6 +90,9 @@ typedef hipError_t (*LaunchFn)(const LaunchArgs& a, int64_t grid, hipStream_t st
 // Internal launch flag (LaunchArgs.flags, above the public scan flags):
 // CONCAT reduce with one workgroup per tile instead of the streaming grid.
 constexpr uint32_t kFlagTilePerBlock = 1u << 16;
+constexpr uint32_t kFlagHasInit = 1u << 17;   // scans: combine init into every output
+constexpr uint32_t kFlagMin = 1u << 18;       // min/max kernels: min (else max)
+constexpr int kAccMinMax = 2;                 // reduce kernels: max / min instead of a sum
 
 // Workgroups of `kernel` (of `threads` threads) that can be resident at once.
 int resident_grid(const void* kernel, int threads = kBlock);
@@ -102,6 +105,8 @@ hipError_t launch_prologue(const LaunchArgs& a, hipStream_t stream);
 // returns nullptr when the combination is not built.
 LaunchFn find_for_each(int in_dt, int out_dt, int op, int items);
 LaunchFn find_reduce(int in_dt, int op, int acc, int items);
+LaunchFn find_reduce_minmax(int in_dt, int op);
+LaunchFn find_scan_minmax(int in_dt, int out_dt);
 LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items);
 LaunchFn find_scan_reduce(int in_dt, int reduce_op, int acc, int items);
 LaunchFn find_broadcast_mul(int in_dt, int op, int items);

@@ -27,6 +27,50 @@ namespace dr {
 template <int IDT>
 using partial_t = typename std::conditional<IDT == DR_I32, int64_t, double>::type;
 
+// Per-thread max (min when mn) of the view values of one tile, each value
+// formed as for_each stores it (binary32 arithmetic for binary32 / bfloat16
+// inputs, binary64 for binary64, exact int64 for int32), widened exactly to
+// the partial type.
+// (si, u0): the tile's geometry; elements outside the segment (loaded as 0)
+// are skipped.
+template <int IDT, int OP, int SLOTS>
+__device__ __forceinline__ partial_t<IDT> thread_tile_minmax(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS],
+                                                            double alpha_d, bool mn, const SegInfo& si,
+                                                            int64_t u0) {
+    constexpr int V = vwidth<IDT>();
+    constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
+    const bool full = tile_full<V, SLOTS>(si, u0);
+    const int w = threadIdx.x >> 6, l = lane_id();
+    if constexpr (IDT == DR_F32 || IDT == DR_BF16) {
+        const float alpha = (float)alpha_d;
+        float m = mm_id<float>(mn);
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const float x1 = ZIP ? decode<IDT>(y[q].e[e]) : 0.0f;
+                const float v = view_apply<OP, float>(decode<IDT>(x[q].e[e]), x1, alpha);
+                if (full || elem_in<V, SLOTS>(si, u0, w, l, q, e, false)) m = mm_op(m, v, mn);
+            }
+        }
+        return (double)m;
+    } else {
+        using P = partial_t<IDT>;
+        const P alpha = (P)alpha_d;
+        P m = mm_id<P>(mn);
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const P x1 = ZIP ? (P)decode<IDT>(y[q].e[e]) : (P)0;
+                const P v = view_apply<OP, P>((P)decode<IDT>(x[q].e[e]), x1, alpha);
+                if (full || elem_in<V, SLOTS>(si, u0, w, l, q, e, false)) m = mm_op(m, v, mn);
+            }
+        }
+        return m;
+    }
+}
+
 // Sum of the view over one tile, returned in thread 0 (whole workgroup).
 template <int IDT, int OP, int ACC, int ITEMS>
 __device__ __forceinline__ partial_t<IDT> tile_partial(const LaunchArgs& a, const SegInfo& si, int64_t t) {
@@ -46,7 +90,16 @@ __device__ __forceinline__ partial_t<IDT> tile_partial(const LaunchArgs& a, cons
     if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, false);
 
     P part = (P)0;
-    if constexpr (F32PATH && ACC == DR_ACC_COMPENSATED) {
+    if constexpr (ACC == kAccMinMax) {
+        const bool mn = (a.flags & kFlagMin) != 0;
+        const P m = wave_reduce_cmb<kCmbMinMax>(thread_tile_minmax<IDT, OP, SLOTS>(x, y, a.alpha, mn, si, u0), mn);
+        if (l == 0) s_wave[w] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            part = mm_id<P>(mn);
+            for (int i = 0; i < WAVES; ++i) part = mm_op(part, s_wave[i], mn);
+        }
+    } else if constexpr (F32PATH && ACC == DR_ACC_COMPENSATED) {
         float s = 0.0f, c = 0.0f;
         comp_accumulate<IDT, OP, SLOTS>(x, y, (float)a.alpha, s, c);
         P tp = (double)s + (double)c;   // exact unless s is not finite
@@ -103,6 +156,7 @@ __device__ __forceinline__ partial_t<IDT> tile_partial(const LaunchArgs& a, cons
 template <int IDT, int OP, int ACC, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_reduce(LaunchArgs a) {
     using P = partial_t<IDT>;
+    constexpr int CMB = ACC == kAccMinMax ? kCmbMinMax : kCmbSum;
     const uint32_t tag = begin_launch(a.ws);
     TileMap tm;
     tm.init(a);
@@ -114,11 +168,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce(LaunchArgs a) {
         if (!tm.find(a, t, si)) return;
         const P part = tile_partial<IDT, OP, ACC, ITEMS>(a, si, t);
         if (threadIdx.x >= 64) return;   // waves 1..3 are done; wave 0 publishes and combines
-        if (a.mode == DR_MODE_BATCH) combine_tile_batch<P>(a, tag, t, si, part);
-        else combine_member<P>(a, tag, 0, 0, t, T, 0, part);
+        if (a.mode == DR_MODE_BATCH) combine_tile_batch<P, CMB>(a, tag, t, si, part);
+        else combine_member<P, CMB>(a, tag, 0, 0, t, T, 0, part);
     } else if (t == 0 && threadIdx.x == 0) {   // no tiles at all
-        if (a.mode == DR_MODE_BATCH) write_all_init<P>(a);
-        else write_result<P>(a, 0, (P)0);
+        if (a.mode == DR_MODE_BATCH) write_all_init<P, CMB>(a);
+        else write_result<P, CMB>(a, 0, cmb_id<CMB, P>((a.flags & kFlagMin) != 0));
     }
 }
 
@@ -175,6 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stream(LaunchArgs a) {
     constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
     constexpr int WAVES = kBlock / 64;
     using P = partial_t<IDT>;
+    constexpr int CMB = ACC == kAccMinMax ? kCmbMinMax : kCmbSum;
     __shared__ P s_wave[WAVES];
     const uint32_t tag = begin_launch(a.ws);
     TileMap tm;
@@ -183,7 +238,15 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stream(LaunchArgs a) {
     const int64_t T = tm.total_tiles;
     const int64_t G = gridDim.x;
     const int w = threadIdx.x >> 6, l = lane_id();
-    P mine = (P)0;
+    const bool mn = (a.flags & kFlagMin) != 0;
+    // the thread's partial over its tiles: a binary64 / int64 sum, or max / min
+    auto merge = [&](P acc, const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS], const SegInfo& si,
+                     int64_t tt) -> P {
+        if constexpr (CMB == kCmbMinMax)
+            return mm_op(acc, thread_tile_minmax<IDT, OP, SLOTS>(x, y, a.alpha, mn, si, (tt - si.first) * a.tile), mn);
+        else return acc + thread_tile_sum<IDT, OP, ACC, SLOTS>(x, y, a.alpha);
+    };
+    P mine = cmb_id<CMB, P>(mn);
     vec<IDT> xa[SLOTS], ya[SLOTS], xb[SLOTS], yb[SLOTS];
     int64_t t = blockIdx.x;
     SegInfo sa, sb;
@@ -199,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stream(LaunchArgs a) {
             load_slots<IDT, SLOTS>(xb, sb.in0, sb, (tb - sb.first) * a.tile, w, l, false);
             if constexpr (ZIP) load_slots<IDT, SLOTS>(yb, sb.in1, sb, (tb - sb.first) * a.tile, w, l, false);
         }
-        mine += thread_tile_sum<IDT, OP, ACC, SLOTS>(xa, ya, a.alpha);
+        mine = merge(mine, xa, ya, sa, t);
         if (!hb) break;
         const int64_t ta = tb + G;
         ha = ta < T && tm.find(a, ta, sa);
@@ -207,17 +270,17 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stream(LaunchArgs a) {
             load_slots<IDT, SLOTS>(xa, sa.in0, sa, (ta - sa.first) * a.tile, w, l, false);
             if constexpr (ZIP) load_slots<IDT, SLOTS>(ya, sa.in1, sa, (ta - sa.first) * a.tile, w, l, false);
         }
-        mine += thread_tile_sum<IDT, OP, ACC, SLOTS>(xb, yb, a.alpha);
+        mine = merge(mine, xb, yb, sb, tb);
         t = ta;
     }
-    const P wsum = wave_sum(mine);
+    const P wsum = wave_reduce_cmb<CMB>(mine, mn);
     if (l == 0) s_wave[w] = wsum;
     __syncthreads();
     if (threadIdx.x >= 64) return;
-    P part = (P)0;
+    P part = cmb_id<CMB, P>(mn);
     if (l == 0)
-        for (int i = 0; i < WAVES; ++i) part += s_wave[i];
-    combine_member<P>(a, tag, 0, 0, blockIdx.x, G, 0, part);
+        for (int i = 0; i < WAVES; ++i) part = cmb_op<CMB>(part, s_wave[i], mn);
+    combine_member<P, CMB>(a, tag, 0, 0, blockIdx.x, G, 0, part);
 }
 
 template <int IDT, int OP, int ACC, int ITEMS>
@@ -246,6 +309,16 @@ hipError_t launch_reduce(const LaunchArgs& a, int64_t grid, hipStream_t stream) 
         default: return nullptr;                                                      \
         }                                                                             \
     }
+
+// max / min reductions (every op, 16 items).
+LaunchFn find_reduce_minmax(int in_dt, int op) {
+    const int items = 16, acc = kAccMinMax;
+    if (in_dt == DR_F32) { DR_RED_OPS(DR_F32, kAccMinMax, 16) }
+    if (in_dt == DR_BF16) { DR_RED_OPS(DR_BF16, kAccMinMax, 16) }
+    if (in_dt == DR_F64) { DR_RED_OPS(DR_F64, kAccMinMax, 16) }
+    if (in_dt == DR_I32) { DR_RED_OPS(DR_I32, kAccMinMax, 16) }
+    return nullptr;
+}
 
 LaunchFn find_reduce(int in_dt, int op, int acc, int items) {
     // integer and binary64 reductions ignore `acc`

@@ -171,6 +171,23 @@ __device__ __forceinline__ typename elem<ODT>::T scan_out(carry_t<IDT, C64> carr
     }
 }
 
+// Output of the generic scan: the sum as above, or max / min of the carry,
+// the wave offset and the prefix inside the wave (exact; int32 outputs hold
+// the int64 value modulo 2^32).
+template <int IDT, int ODT, bool C64, int CMB>
+__device__ __forceinline__ typename elem<ODT>::T scan_out_cmb(carry_t<IDT, C64> carry, local_t<IDT> woff,
+                                                               local_t<IDT> pre, bool mn) {
+    if constexpr (CMB == kCmbSum) {
+        return scan_out<IDT, ODT, C64>(carry, woff, pre);
+    } else {
+        using C = carry_t<IDT, C64>;
+        using O = typename elem<ODT>::T;
+        const C v = mm_op(carry, mm_op((C)woff, (C)pre, mn), mn);
+        if constexpr (ODT == DR_I32) return (int32_t)(uint32_t)(uint64_t)v;
+        else return (O)v;
+    }
+}
+
 // Per-thread sum of ROP over the zipped (in0, in1) elements of a loaded
 // tile, accumulated as RACC (the fused reduction; order-insensitive, so it
 // is taken before the scan values replace the loaded ones).
@@ -206,51 +223,75 @@ __device__ __forceinline__ double fused_partial(const vec<IDT> (&x)[SLOTS], cons
 // offset of the slot's first element inside the wave is kept (base[s]);
 // the serial prefix inside the slot is recomputed, in the same order, when
 // the outputs are formed. Returns the wave's total (every lane).
-template <int IDT, int OP, bool ZIP, int SLOTS, bool REV>
+// (si, u0, full): the tile's geometry. Elements outside the segment (only
+// in tiles that are not full) were loaded as 0: the identity of a sum, and
+// replaced by the operator's identity otherwise.
+template <int IDT, int OP, bool ZIP, int SLOTS, bool REV, int CMB = kCmbSum>
 __device__ __forceinline__ local_t<IDT> tile_values(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS],
                                                     local_t<IDT> alpha, local_t<IDT> (&v)[SLOTS][vwidth<IDT>()],
-                                                    local_t<IDT> (&base)[SLOTS]) {
+                                                    local_t<IDT> (&base)[SLOTS], bool mn, const SegInfo& si,
+                                                    int64_t u0, bool full) {
     constexpr int V = vwidth<IDT>();
     using L = local_t<IDT>;
-    L run = (L)0;
+    const L id = cmb_id<CMB, L>(mn);
+    const int w = threadIdx.x >> 6, l = lane_id();
+    L run = id;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
 #pragma unroll
-        for (int e = 0; e < V; ++e)
+        for (int e = 0; e < V; ++e) {
             v[s][e] = scan_value<IDT, OP, L>(x[s].e[e], ZIP ? y[s].e[e] : zero_elem<IDT>(), alpha);
+            if constexpr (CMB != kCmbSum)
+                if (!full && !elem_in<V, SLOTS>(si, u0, w, l, s, e, REV)) v[s][e] = id;
+        }
         mirror_if(v[s], REV);
         L tot = v[s][0];
 #pragma unroll
-        for (int e = 1; e < V; ++e) tot = tot + v[s][e];
-        const L inc = wave_incl_scan(tot);
-        base[s] = run + shfl_up1(inc);
-        run = run + readlane(inc, 63);
+        for (int e = 1; e < V; ++e) tot = cmb_op<CMB>(tot, v[s][e], mn);
+        const L inc = wave_incl_scan_cmb<CMB>(tot, mn);
+        L up = __shfl_up(inc, 1, 64);
+        if (lane_id() == 0) up = id;
+        base[s] = cmb_op<CMB>(run, up, mn);
+        run = cmb_op<CMB>(run, readlane(inc, 63), mn);
     }
     return run;
 }
 
 // Outputs of a tile: carry + offset of the wave + prefix inside the wave.
-template <int IDT, int ODT, bool C64, int SLOTS, bool REV>
+// `exc`: exclusive scan (each output combines the elements strictly before
+// it in processing order).
+template <int IDT, int ODT, bool C64, int SLOTS, bool REV, int CMB = kCmbSum>
 __device__ __forceinline__ void tile_write(const local_t<IDT> (&v)[SLOTS][vwidth<IDT>()],
                                            const local_t<IDT> (&base)[SLOTS], carry_t<IDT, C64> excl,
                                            local_t<IDT> woff, const SegInfo& si, int64_t u0, int w, int l,
-                                           bool full) {
+                                           bool full, bool exc = false, bool mn = false) {
     constexpr int V = vwidth<IDT>();
     using L = local_t<IDT>;
     using O = typename elem<ODT>::T;
+    const L id = cmb_id<CMB, L>(mn);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         O o[V];
-        L pre = v[s][0];
-        o[0] = scan_out<IDT, ODT, C64>(excl, woff, base[s] + pre);
+        L pre = v[s][0];       // inclusive prefix inside the slot
+        L before = id;         // exclusive prefix inside the slot
+        o[0] = scan_out_cmb<IDT, ODT, C64, CMB>(excl, woff, exc ? base[s] : cmb_op<CMB>(base[s], pre, mn), mn);
 #pragma unroll
         for (int e = 1; e < V; ++e) {
-            pre = pre + v[s][e];
-            o[e] = scan_out<IDT, ODT, C64>(excl, woff, base[s] + pre);
+            before = pre;
+            pre = cmb_op<CMB>(pre, v[s][e], mn);
+            o[e] = scan_out_cmb<IDT, ODT, C64, CMB>(excl, woff, cmb_op<CMB>(base[s], exc ? before : pre, mn), mn);
         }
+        (void)before;
         mirror_if(o, REV);
         store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, REV, full, o);
     }
+}
+
+// The caller's initial value in the carry type (scans with kFlagHasInit).
+template <class C, int IDT>
+__device__ __forceinline__ C init_carry(const LaunchArgs& a) {
+    if constexpr (IDT == DR_I32) return (C)a.init_i;
+    else return (C)a.init_f;
 }
 
 template <int IDT, int OP, bool FUSED, int ROP>
@@ -294,7 +335,7 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
 
     L v[SLOTS][V];
     L base[SLOTS];
-    const L run = tile_values<IDT, OP, ZIP, SLOTS, REV>(x, y, (L)a.alpha, v, base);
+    const L run = tile_values<IDT, OP, ZIP, SLOTS, REV>(x, y, (L)a.alpha, v, base, false, si, u0, full);
     if (l == 0) s_wtot[w] = run;
     __syncthreads();
 
@@ -315,7 +356,9 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
         if (l == 0) s_red[w] = wr;
         __syncthreads();
     }
-    tile_write<IDT, ODT, C64, SLOTS, REV>(v, base, excl, woff, si, u0, w, l, full);
+    // the initial value reaches the outputs only, never the published carries
+    const C eo = (a.flags & kFlagHasInit) ? init_carry<C, IDT>(a) + excl : excl;
+    tile_write<IDT, ODT, C64, SLOTS, REV>(v, base, eo, woff, si, u0, w, l, full, (a.flags & DR_SCAN_EXCLUSIVE) != 0);
     double part = 0.0;
     if constexpr (FUSED) {
         if (threadIdx.x == 0)
@@ -401,7 +444,7 @@ constexpr int kChunkHdr = 4;
 constexpr int kRecCarry = 0;
 constexpr int kRecHead = 1;
 
-template <int IDT, int OP, bool C64, int ITEMS, bool REV>
+template <int IDT, int OP, bool C64, int ITEMS, bool REV, int CMB>
 __global__ __launch_bounds__(kBlock) void k_scan_sums(LaunchArgs a) {
     constexpr int V = vwidth<IDT>();
     constexpr int SLOTS = ITEMS / V;
@@ -428,8 +471,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_sums(LaunchArgs a) {
     const int64_t r1 = r0 + Q < T ? r0 + Q : T;
     const int w = threadIdx.x >> 6, l = lane_id();
     const L alpha = (L)a.alpha;
+    const bool mn = (a.flags & kFlagMin) != 0;
 
-    C run = (C)0;    // thread 0: carry of the next tile relative to the chunk / head
+    C run = cmb_id<CMB, C>(mn);    // thread 0: carry of the next tile relative to the chunk / head
     bool seen = false;
     vec<IDT> xa[SLOTS], ya[SLOTS], xb[SLOTS], yb[SLOTS];
     SegInfo sa, sb;
@@ -451,23 +495,25 @@ __global__ __launch_bounds__(kBlock) void k_scan_sums(LaunchArgs a) {
         if (ok) {
             L v[SLOTS][V];
             L base[SLOTS];
-            const L wt = tile_values<IDT, OP, ZIP, SLOTS, REV>(x, y, alpha, v, base);
+            const int64_t u0 = (tile_of(rr) - si.first) * a.tile;
+            const L wt = tile_values<IDT, OP, ZIP, SLOTS, REV, CMB>(x, y, alpha, v, base, mn, si, u0,
+                                                                    tile_full<V, SLOTS>(si, u0));
             if (l == 0) s_wtot[i & 1][w] = wt;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            L tl = (L)0;
+            L tl = cmb_id<CMB, L>(mn);
             if (ok)
-                for (int k = 0; k < WAVES; ++k) tl += s_wtot[i & 1][k];
+                for (int k = 0; k < WAVES; ++k) tl = cmb_op<CMB>(tl, s_wtot[i & 1][k], mn);
             const bool head = !ok || rr == stop_of<REV>(a, si, T);
             if (head) {
-                run = (C)0;
+                run = cmb_id<CMB, C>(mn);
                 seen = true;
             }
             uint64_t* rec = tws + rr * TW;
             rec[kRecCarry] = to_bits(run);
             rec[kRecHead] = seen ? 1u : 0u;
-            run = run + (C)tl;
+            run = cmb_op<CMB>(run, (C)tl, mn);
         }
     };
     if (r < r1) ha = issue(r, sa, xa, ya);
@@ -491,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_sums(LaunchArgs a) {
 // (f1, s1) then (f2, s2) = (f1 | f2, f2 ? s2 : s1 + s2).
 constexpr int kScanChunkThreads = 1024;
 
-template <class C>
+template <class C, int CMB>
 __global__ __launch_bounds__(kScanChunkThreads) void k_scan_chunks(LaunchArgs a) {
     constexpr int N = kScanChunkThreads;
     __shared__ C s_v[2][N];
@@ -500,16 +546,18 @@ __global__ __launch_bounds__(kScanChunkThreads) void k_scan_chunks(LaunchArgs a)
     const int64_t G = cw[1] < (uint64_t)kMaxChunks ? (int64_t)cw[1] : kMaxChunks;
     const int tid = threadIdx.x;
     const int64_t K = (G + N - 1) / N;   // chunks per thread (consecutive)
+    const bool mn = (a.flags & kFlagMin) != 0;
+    const C id = cmb_id<CMB, C>(mn);
     // serial inclusive pair of this thread's chunks
     bool f = false;
-    C sv = (C)0;
+    C sv = id;
     for (int64_t j = 0; j < K; ++j) {
         const int64_t c = tid * K + j;
         if (c >= G) break;
         const uint64_t* cr = cw + kChunkHdr + 4 * c;
         const bool fc = cr[0] != 0;
         const C vc = from_bits<C>(cr[1]);
-        sv = fc ? vc : sv + vc;
+        sv = fc ? vc : cmb_op<CMB>(sv, vc, mn);
         f = f || fc;
     }
     // inclusive scan of the thread pairs (Hillis-Steele, double-buffered)
@@ -521,7 +569,7 @@ __global__ __launch_bounds__(kScanChunkThreads) void k_scan_chunks(LaunchArgs a)
         C v = s_v[cur][tid];
         uint8_t fl = s_f[cur][tid];
         if (tid >= d && !fl) {
-            v = s_v[cur][tid - d] + v;
+            v = cmb_op<CMB>(s_v[cur][tid - d], v, mn);
             fl = s_f[cur][tid - d];
         }
         s_v[cur ^ 1][tid] = v;
@@ -530,18 +578,18 @@ __global__ __launch_bounds__(kScanChunkThreads) void k_scan_chunks(LaunchArgs a)
         __syncthreads();
     }
     // exclusive carry into this thread's first chunk, then serially on
-    C cin = tid > 0 ? s_v[cur][tid - 1] : (C)0;
+    C cin = tid > 0 ? s_v[cur][tid - 1] : id;
     for (int64_t j = 0; j < K; ++j) {
         const int64_t c = tid * K + j;
         if (c >= G) break;
         uint64_t* cr = cw + kChunkHdr + 4 * c;
         cr[2] = to_bits(cin);
         const C vc = from_bits<C>(cr[1]);
-        cin = cr[0] != 0 ? vc : cin + vc;
+        cin = cr[0] != 0 ? vc : cmb_op<CMB>(cin, vc, mn);
     }
 }
 
-template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
+template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV, int CMB>
 __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
     constexpr int V = vwidth<IDT>();
     constexpr int SLOTS = ITEMS / V;
@@ -583,19 +631,22 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
     if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, REV);
     double rpart_thread = 0.0;
     if constexpr (FUSED) rpart_thread = fused_partial<IDT, ROP, RACC, SLOTS>(x, y);
+    const bool mn = (a.flags & kFlagMin) != 0;
     L v[SLOTS][V];
     L base[SLOTS];
-    const L run = tile_values<IDT, OP, ZIP, SLOTS, REV>(x, y, (L)a.alpha, v, base);
+    const L run = tile_values<IDT, OP, ZIP, SLOTS, REV, CMB>(x, y, (L)a.alpha, v, base, mn, si, u0, full);
     if (l == 0) s_wtot[w] = run;
     if constexpr (FUSED) {
         const double wr = wave_sum(rpart_thread);
         if (l == 0) s_red[w] = wr;
     }
     __syncthreads();
-    L woff = (L)0;
-    for (int i = 0; i < w; ++i) woff += s_wtot[i];
-    const C excl = rh ? from_bits<C>(rc) : from_bits<C>(rc) + from_bits<C>(ci);
-    tile_write<IDT, ODT, C64, SLOTS, REV>(v, base, excl, woff, si, u0, w, l, full);
+    L woff = cmb_id<CMB, L>(mn);
+    for (int i = 0; i < w; ++i) woff = cmb_op<CMB>(woff, s_wtot[i], mn);
+    C excl = rh ? from_bits<C>(rc) : cmb_op<CMB>(from_bits<C>(rc), from_bits<C>(ci), mn);
+    if (a.flags & kFlagHasInit) excl = cmb_op<CMB>(init_carry<C, IDT>(a), excl, mn);
+    tile_write<IDT, ODT, C64, SLOTS, REV, CMB>(v, base, excl, woff, si, u0, w, l, full,
+                                               (a.flags & DR_SCAN_EXCLUSIVE) != 0, mn);
     if constexpr (FUSED) {
         if (threadIdx.x >= 64) return;   // wave 0 publishes the partial and combines
         double part = 0.0;
@@ -606,40 +657,43 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
     }
 }
 
-template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
+template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV, int CMB>
 hipError_t launch_scan_dir(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
-    if (a.flags & kFlagTilePerBlock) {
-        hipLaunchKernelGGL((k_scan<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, REV>), dim3((uint32_t)grid),
-                           dim3(kBlock), 0, stream, a);
-        return hipGetLastError();
+    if constexpr (CMB == kCmbSum) {
+        if (a.flags & kFlagTilePerBlock) {
+            hipLaunchKernelGGL((k_scan<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, REV>), dim3((uint32_t)grid),
+                               dim3(kBlock), 0, stream, a);
+            return hipGetLastError();
+        }
     }
     using C = carry_t<IDT, C64>;
-    static const int resident = resident_grid((const void*)k_scan_sums<IDT, OP, C64, ITEMS, REV>);
+    static const int resident = resident_grid((const void*)k_scan_sums<IDT, OP, C64, ITEMS, REV, CMB>);
     int64_t g1 = resident < kMaxChunks ? resident : kMaxChunks;
     if (g1 > grid) g1 = grid;
     if (g1 < 1) g1 = 1;
-    hipLaunchKernelGGL((k_scan_sums<IDT, OP, C64, ITEMS, REV>), dim3((uint32_t)g1), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL((k_scan_sums<IDT, OP, C64, ITEMS, REV, CMB>), dim3((uint32_t)g1), dim3(kBlock), 0, stream,
+                       a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scan_chunks<C>), dim3(1), dim3(kScanChunkThreads), 0, stream, a);
+    hipLaunchKernelGGL((k_scan_chunks<C, CMB>), dim3(1), dim3(kScanChunkThreads), 0, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scan_apply<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, REV>), dim3((uint32_t)grid),
-                       dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL((k_scan_apply<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, REV, CMB>),
+                       dim3((uint32_t)grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
-template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS>
+template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, int CMB = kCmbSum>
 hipError_t launch_scan(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
     // the prologue (epoch tag, zeroed counters) serves the single-pass form
     // and the fused reduction's combine
-    if (FUSED || (a.flags & kFlagTilePerBlock)) {
+    if (FUSED || (CMB == kCmbSum && (a.flags & kFlagTilePerBlock))) {
         hipError_t e = launch_prologue(a, stream);
         if (e != hipSuccess) return e;
     }
     if (a.flags & DR_SCAN_REVERSE)
-        return launch_scan_dir<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, true>(a, grid, stream);
-    return launch_scan_dir<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, false>(a, grid, stream);
+        return launch_scan_dir<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, true, CMB>(a, grid, stream);
+    return launch_scan_dir<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, false, CMB>(a, grid, stream);
 }
 
 #define DR_SCAN_OPS(IDT, ODT, C64, ITEMS)                                                           \
@@ -674,6 +728,21 @@ LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items) {
     DR_SCAN_ID(DR_BF16, DR_F32, true, 64)
     DR_SCAN_OPS(DR_F64, DR_F64, true, 16)
     DR_SCAN_ID(DR_F64, DR_F64, true, 32)
+    return nullptr;
+}
+
+// max / min scans: the identity view, reduce-then-scan form, 16 items.
+LaunchFn find_scan_minmax(int in_dt, int out_dt) {
+    if (in_dt == DR_I32 && out_dt == DR_I64)
+        return launch_scan<DR_I32, DR_I64, DR_OP_IDENTITY, true, false, 0, 0, 16, kCmbMinMax>;
+    if (in_dt == DR_I32 && out_dt == DR_I32)
+        return launch_scan<DR_I32, DR_I32, DR_OP_IDENTITY, true, false, 0, 0, 16, kCmbMinMax>;
+    if (in_dt == DR_F32 && out_dt == DR_F32)
+        return launch_scan<DR_F32, DR_F32, DR_OP_IDENTITY, true, false, 0, 0, 16, kCmbMinMax>;
+    if (in_dt == DR_BF16 && out_dt == DR_F32)
+        return launch_scan<DR_BF16, DR_F32, DR_OP_IDENTITY, true, false, 0, 0, 16, kCmbMinMax>;
+    if (in_dt == DR_F64 && out_dt == DR_F64)
+        return launch_scan<DR_F64, DR_F64, DR_OP_IDENTITY, true, false, 0, 0, 16, kCmbMinMax>;
     return nullptr;
 }
 

@@ -178,3 +178,34 @@ def test_tuning_supported_table():
     vs = B.make_view("identity", B.DR_I32)
     assert L.dr_tuning_supported(B.DR_ALGO_SCAN, ctypes.byref(vs), B.DR_I64, None) == 1
     assert L.dr_tuning_supported(B.DR_ALGO_SCAN, ctypes.byref(vs), B.DR_F32, None) == 0
+
+
+def test_generic_operator_argument_errors():
+    """dr_scan / dr_reduce reject what they do not support before anything
+    is enqueued (every call here fails a host check)."""
+    L = B.lib()
+    t, keep = _host_table([((A,), (O,), 10)], 10)
+    v = B.make_view("identity", B.DR_F32)
+    sq = B.make_view("square", B.DR_F32)
+    init = ctypes.c_double(1.5)
+
+    def scan(view, combine, flags=0, tuning=None, out=B.DR_F32):
+        return L.dr_scan(ctypes.byref(t), ctypes.byref(view), out, combine, flags, ctypes.byref(init),
+                         0x40000000, 1 << 30, ctypes.byref(tuning) if tuning else None, None)
+
+    assert scan(v, 7) == -1 and b"combine" in L.dr_last_error()
+    assert scan(v, B.DR_COMBINE_SUM, flags=0x40) == -1                       # unknown flag
+    assert scan(sq, B.DR_COMBINE_MAX) == -2 and b"identity" in L.dr_last_error()
+    assert scan(v, B.DR_COMBINE_MIN, flags=B.DR_SCAN_CARRY_F32) == -2
+    assert scan(v, B.DR_COMBINE_MAX, tuning=B.make_tuning(16, B.DR_TUNE_TILE_PER_BLOCK)) == -2
+    assert scan(v, B.DR_COMBINE_MAX, tuning=B.make_tuning(64)) == -2
+    assert scan(v, B.DR_COMBINE_MAX, out=B.DR_I64) == -2                     # f32 -> i64 not a scan pair
+    # the exclusive flag belongs to dr_scan, not dr_inclusive_scan
+    assert _call_scan(t, v, flags=B.DR_SCAN_EXCLUSIVE) == -1
+    tr, keep2 = _host_table([((A,), (), 10)], 10)
+    assert L.dr_reduce(ctypes.byref(tr), ctypes.byref(v), 9, 0, None, O, 0x40000000, 1 << 30, None, None) == -1
+    assert L.dr_reduce(ctypes.byref(tr), ctypes.byref(v), B.DR_COMBINE_MAX, 0, None, None, 0x40000000, 1 << 30,
+                       None, None) == -1                                     # result NULL
+    assert L.dr_reduce(ctypes.byref(tr), ctypes.byref(v), B.DR_COMBINE_MIN, 0, None, O, 0x40000000, 1 << 30,
+                       ctypes.byref(B.make_tuning(32)), None) == -2
+    del keep, keep2
