@@ -732,15 +732,18 @@ LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items) {
 }
 
 // max / min scans: the identity view, reduce-then-scan form, 16 items.
+// binary32 / bfloat16 inputs keep binary32 carries: rounding is monotone, so
+// the max (min) of binary32 values and a rounded init equals the rounding of
+// the exact max (min) in binary64.
 LaunchFn find_scan_minmax(int in_dt, int out_dt) {
     if (in_dt == DR_I32 && out_dt == DR_I64)
         return launch_scan<DR_I32, DR_I64, DR_OP_IDENTITY, true, false, 0, 0, 16, kCmbMinMax>;
     if (in_dt == DR_I32 && out_dt == DR_I32)
         return launch_scan<DR_I32, DR_I32, DR_OP_IDENTITY, true, false, 0, 0, 16, kCmbMinMax>;
     if (in_dt == DR_F32 && out_dt == DR_F32)
-        return launch_scan<DR_F32, DR_F32, DR_OP_IDENTITY, true, false, 0, 0, 16, kCmbMinMax>;
+        return launch_scan<DR_F32, DR_F32, DR_OP_IDENTITY, false, false, 0, 0, 16, kCmbMinMax>;
     if (in_dt == DR_BF16 && out_dt == DR_F32)
-        return launch_scan<DR_BF16, DR_F32, DR_OP_IDENTITY, true, false, 0, 0, 16, kCmbMinMax>;
+        return launch_scan<DR_BF16, DR_F32, DR_OP_IDENTITY, false, false, 0, 0, 16, kCmbMinMax>;
     if (in_dt == DR_F64 && out_dt == DR_F64)
         return launch_scan<DR_F64, DR_F64, DR_OP_IDENTITY, true, false, 0, 0, 16, kCmbMinMax>;
     return nullptr;
