@@ -59,6 +59,7 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_reduce_grad.argtypes = [i, PP, PP, PP, I64P, i, i, d, i, DP, i]
         _lib.oracle_reduce_ex.argtypes = [i, PP, PP, I64P, i, i, d, i, i, i, i64, d, I64P, DP]
         _lib.oracle_scan_ex.argtypes = [i, PP, PP, PP, PP, I64P, i, i, d, i, i, i, i, i, i, i64, d]
+        _lib.oracle_black_scholes.argtypes = [i, PP, PP, PP, PP, PP, PP, I64P, d]
         for f in ("oracle_for_each", "oracle_reduce", "oracle_scan", "oracle_reduce_grad"):
             getattr(_lib, f).restype = i
     return _lib
@@ -192,4 +193,16 @@ def scan_ex(in0, in1, in_dtype, op, combine, mode=CONCAT, reverse=False, exclusi
                                 in_dtype, op, float(alpha), mode, int(bool(reverse)), out_dtype, combine,
                                 int(bool(exclusive)), has, ii, ff))
     return (outs, absp) if want_abs else outs
+
+
+def black_scholes(S, K, T, V, r):
+    """Per-segment (call, put) binary64 prices of European options for the
+    binary32 arrays S (spot), K (strike), T (years), V (volatility) and the
+    rate r."""
+    S, K, T, V = (_prep(a, F32) for a in (S, K, T, V))
+    calls = [np.empty(a.shape[0], dtype=np.float64) for a in S]
+    puts = [np.empty(a.shape[0], dtype=np.float64) for a in S]
+    _check(lib().oracle_black_scholes(len(S), _ptrs(S), _ptrs(K), _ptrs(T), _ptrs(V), _ptrs(calls), _ptrs(puts),
+                                      _lengths(S), float(r)))
+    return calls, puts
 

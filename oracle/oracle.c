@@ -575,4 +575,42 @@ int oracle_scan_ex(int m, const void* const* in0, const void* const* in1,
     return OR_OK;
 }
 
+/* ---- Black-Scholes for_each (section 5, "Black Scholes") ----------------- */
+
+/*
+ * The paper's Black Scholes benchmark is a for_each over a zip of option
+ * arrays that prices European options. The price is the standard closed-form
+ * solution of the Black-Scholes equation: for spot S, strike K, time to
+ * expiry T (years), volatility sigma and risk-free rate r,
+ *   d1 = (ln(S/K) + (r + sigma^2/2) T) / (sigma sqrt(T)),   d2 = d1 - sigma sqrt(T),
+ *   call = S N(d1) - K exp(-rT) N(d2),   put = K exp(-rT) N(-d2) - S N(-d1),
+ * N the standard normal distribution function, N(x) = erfc(-x / sqrt(2)) / 2.
+ * Inputs are the stored binary32 values; the prices are evaluated in
+ * binary64 with the C library's log, sqrt, exp and erfc.
+ */
+int oracle_black_scholes(int m, const float* const* S, const float* const* K, const float* const* T,
+                         const float* const* V, double* const* call, double* const* put,
+                         const int64_t* len, double r)
+{
+    if (m < 0 || len == 0)
+        return OR_EBADARG;
+    const double rs2 = 0.70710678118654752440;   /* 1 / sqrt(2) */
+    for (int k = 0; k < m; ++k) {
+        if (len[k] < 0)
+            return OR_EBADARG;
+        if (len[k] > 0 && (!S[k] || !K[k] || !T[k] || !V[k] || !call[k] || !put[k]))
+            return OR_EBADARG;
+        for (int64_t j = 0; j < len[k]; ++j) {
+            double s = S[k][j], x = K[k][j], t = T[k][j], v = V[k][j];
+            double vst = v * sqrt(t);
+            double d1 = (log(s / x) + (r + 0.5 * v * v) * t) / vst;
+            double d2 = d1 - vst;
+            double disc = exp(-r * t);
+            call[k][j] = s * 0.5 * erfc(-d1 * rs2) - x * disc * 0.5 * erfc(-d2 * rs2);
+            put[k][j] = x * disc * 0.5 * erfc(d2 * rs2) - s * 0.5 * erfc(d1 * rs2);
+        }
+    }
+    return OR_OK;
+}
+
 int oracle_abi_version(void) { return 1; }

@@ -227,3 +227,22 @@ def batch(count: int = BATCH_RANGES, total: int = BATCH_TOTAL, max_len: int = BA
     n = sum(lengths)
     return {"lengths": lengths, "x": normal_f32(n, seed + 100),
             "y": normal_f32(n, seed + 200)}
+
+
+OPTIONS_N = 1 << 28
+OPTIONS_SEGMENTS = 8
+OPTIONS_RATE = 0.02
+SEED_OPTIONS = 1006
+
+
+def options(n: int = OPTIONS_N, segments: int = OPTIONS_SEGMENTS, seed: int = SEED_OPTIONS) -> dict:
+    """European options for the Black-Scholes for_each: binary32 spot S and
+    strike K U[10, 50), time to expiry T U[0.1, 2) years, volatility
+    V U[0.1, 0.5), one risk-free rate; equal segments."""
+    g = rng(seed)
+    return {"lengths": lengths_block(n, segments),
+            "S": g.uniform(10.0, 50.0, size=n).astype(np.float32),
+            "K": g.uniform(10.0, 50.0, size=n).astype(np.float32),
+            "T": g.uniform(0.1, 2.0, size=n).astype(np.float32),
+            "V": g.uniform(0.1, 0.5, size=n).astype(np.float32),
+            "r": OPTIONS_RATE}

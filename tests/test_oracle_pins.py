@@ -541,3 +541,58 @@ def test_sum_with_init_matches_fsum():
     for i in (0, 1, 17, 2499, 4999):
         want = math.fsum([init] + [float(v) for v in x[:i]])
         assert abs(ex[i] - want) <= 2 * U64 * (abs(init) + float(np.abs(x[:i].astype(np.float64)).sum()))
+
+
+# --- Black-Scholes (section 5, "Black Scholes") -----------------------------------
+
+def _bs(S, K, T, V, r):
+    f = lambda a: [np.asarray(a, dtype=np.float32)]
+    c, p = O.black_scholes(f(S), f(K), f(T), f(V), r)
+    return c[0], p[0]
+
+
+def test_black_scholes_textbook_example():
+    """The standard textbook example (S = 42, K = 40, r = 0.1, sigma = 0.2,
+    T = 0.5) prices the call at 4.76 and the put at 0.81."""
+    c, p = _bs([42.0], [40.0], [0.5], [0.2], 0.1)
+    assert round(float(c[0]), 2) == 4.76 and round(float(p[0]), 2) == 0.81
+
+
+def test_black_scholes_put_call_parity_and_bounds():
+    t = I.options(n=20000, segments=4, seed=7)
+    c, p = _bs(t["S"], t["K"], t["T"], t["V"], t["r"])
+    S, K, T = (t[n].astype(np.float64) for n in ("S", "K", "T"))
+    fwd = S - K * np.exp(-t["r"] * T)
+    assert np.all(np.abs((c - p) - fwd) <= 1e-12 * (S + K))
+    # no-arbitrage bounds: max(S - K e^{-rT}, 0) <= call <= S; max(-fwd, 0) <= put <= K e^{-rT}
+    assert np.all(c >= np.maximum(fwd, 0) - 1e-12 * S) and np.all(c <= S)
+    assert np.all(p >= np.maximum(-fwd, 0) - 1e-12 * K) and np.all(p <= K * np.exp(-t["r"] * T) + 1e-12 * K)
+
+
+def test_black_scholes_at_the_money_closed_form():
+    """With r = 0 and S = K the call is S erf(sigma sqrt(T) / (2 sqrt 2))."""
+    for S, T, V in ((10.0, 1.0, 0.2), (37.5, 0.25, 0.45), (12.0, 2.0, 0.1)):
+        c, p = _bs([S], [S], [T], [V], 0.0)
+        want = S * math.erf(float(np.float32(V)) * math.sqrt(float(np.float32(T))) / (2 * math.sqrt(2)))
+        assert abs(c[0] - want) <= 1e-13 * S and abs(p[0] - want) <= 1e-13 * S
+
+
+def test_black_scholes_matches_scipy_normal_cdf():
+    from scipy.stats import norm
+    t = I.options(n=5000, segments=1, seed=8)
+    c, p = _bs(t["S"], t["K"], t["T"], t["V"], t["r"])
+    S, K, T, V = (t[n].astype(np.float64) for n in ("S", "K", "T", "V"))
+    r = t["r"]
+    d1 = (np.log(S / K) + (r + V * V / 2) * T) / (V * np.sqrt(T))
+    d2 = d1 - V * np.sqrt(T)
+    wc = S * norm.cdf(d1) - K * np.exp(-r * T) * norm.cdf(d2)
+    wp = K * np.exp(-r * T) * norm.cdf(-d2) - S * norm.cdf(-d1)
+    assert np.all(np.abs(c - wc) <= 1e-12 * (S + K)) and np.all(np.abs(p - wp) <= 1e-12 * (S + K))
+
+
+def test_black_scholes_deterministic_limit():
+    """As sigma sqrt(T) -> 0 the call tends to max(S - K e^{-rT}, 0)."""
+    c, p = _bs([50.0, 10.0], [10.0, 50.0], [0.01, 0.01], [0.001, 0.001], 0.05)
+    disc = math.exp(-0.05 * float(np.float32(0.01)))      # T as stored (binary32), widened first
+    assert abs(c[0] - (50 - 10 * disc)) < 1e-12 and c[1] < 1e-12
+    assert p[0] < 1e-12 and abs(p[1] - (50 * disc - 10)) < 1e-12
