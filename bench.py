@@ -296,6 +296,19 @@ def configs_report(reps: int) -> int:
     report("C5 batch", "fused scan + dot, one call per range (10,000 calls)", 12 * n5, lambda: [
         B.dr_scan_reduce(tb, vid, vmul, B.DR_ACC_COMPENSATED, 0.0, rr, workspace=ws1, host_check=False)
         for tb, rr in per], n_reps=2)
+    del x, y, s5, gx, gy, per, tab, tsc, tdt, tbm, trs
+
+    # Black-Scholes for_each (the paper's Black Scholes benchmark): 2^28
+    # options, 8 equal segments; 16 bytes read and 8 written per option
+    t = I.options()
+    L = t["lengths"]
+    ins = [to_dev(t[n]) for n in ("S", "K", "T", "V")]
+    call, put = torch.empty_like(ins[0]), torch.empty_like(ins[0])
+    tbs = B.segments([pieces(a, L) for a in ins], [pieces(call, L), pieces(put, L)])
+    report("Black-Scholes", "2^28 options: call and put", 24 * sum(L), lambda: B.dr_for_each(
+        tbs, B.make_view("black_scholes", B.DR_F32, t["r"]), B.DR_F32, host_check=False))
+    del t, ins, call, put, tbs
+
     flags = 0
     for w_ in (ws, ws5, ws1, ws_s, ws_d, ws_b, ws_r):
         flags |= w_.device_status()

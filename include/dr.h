@@ -91,7 +91,17 @@ typedef enum dr_op {
     DR_OP_IDENTITY = 0,
     DR_OP_SQUARE = 1,
     DR_OP_MUL = 2,
-    DR_OP_AXPY = 3
+    DR_OP_AXPY = 3,
+    /* Black-Scholes prices of European options (the paper's Black Scholes
+     * for_each benchmark, section 5): arity 4, in[0] spot S, in[1] strike K,
+     * in[2] time to expiry T (years), in[3] volatility sigma; alpha is the
+     * risk-free rate r. dr_for_each only, binary32 in and out, two outputs:
+     * out[0] the call price S N(d1) - K exp(-rT) N(d2), out[1] the put price
+     * K exp(-rT) N(-d2) - S N(-d1), with d1 = (ln(S/K) + (r + sigma^2/2) T)
+     * / (sigma sqrt(T)), d2 = d1 - sigma sqrt(T) and N the standard normal
+     * distribution function, evaluated in binary32 with the device's log,
+     * sqrt, exp and erfc. */
+    DR_OP_BLACK_SCHOLES = 4
 } dr_op;
 
 /* Floating-point accumulation of a reduction. PLAIN: binary32 sums inside a

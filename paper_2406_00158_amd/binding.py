@@ -33,13 +33,15 @@ DR_ALGO_FOR_EACH, DR_ALGO_REDUCE, DR_ALGO_SCAN, DR_ALGO_SCAN_REDUCE, DR_ALGO_BRO
 DR_SMALL_TABLE = 64
 DR_MAX_ARITY = 4
 DR_MAX_OUTPUTS = 2
-OP_ARITY = {DR_OP_IDENTITY: 1, DR_OP_SQUARE: 1, DR_OP_MUL: 2, DR_OP_AXPY: 2}
+DR_OP_BLACK_SCHOLES = 4
+OP_ARITY = {DR_OP_IDENTITY: 1, DR_OP_SQUARE: 1, DR_OP_MUL: 2, DR_OP_AXPY: 2, DR_OP_BLACK_SCHOLES: 4}
 
 TORCH_DTYPE = {DR_I32: torch.int32, DR_F32: torch.float32, DR_BF16: torch.bfloat16,
                DR_F64: torch.float64, DR_I64: torch.int64}
 DR_DTYPE = {v: k for k, v in TORCH_DTYPE.items()}
 
-OPS = {"identity": DR_OP_IDENTITY, "square": DR_OP_SQUARE, "mul": DR_OP_MUL, "axpy": DR_OP_AXPY}
+OPS = {"identity": DR_OP_IDENTITY, "square": DR_OP_SQUARE, "mul": DR_OP_MUL, "axpy": DR_OP_AXPY,
+       "black_scholes": DR_OP_BLACK_SCHOLES}
 ACCS = {"plain": DR_ACC_PLAIN, "compensated": DR_ACC_COMPENSATED}
 MODES = {"concat": DR_MODE_CONCAT, "batch": DR_MODE_BATCH}
 

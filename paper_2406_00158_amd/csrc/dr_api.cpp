@@ -58,6 +58,7 @@ int op_arity(int op) {
     case DR_OP_SQUARE: return 1;
     case DR_OP_MUL: return 2;
     case DR_OP_AXPY: return 2;
+    case DR_OP_BLACK_SCHOLES: return 4;
     default: return 0;
     }
 }
@@ -367,16 +368,20 @@ dr_status dr_for_each(const dr_table* table, const dr_view* view, int32_t out_dt
     dr_status s = check_view(view, true);
     if (s) return s;
     const int in = view->in_dtype;
+    const bool bs = view->op == DR_OP_BLACK_SCHOLES;
+    if (bs && (in != DR_F32 || out_dtype != DR_F32))
+        return fail(DR_ERR_UNSUPPORTED, "the Black-Scholes view is built for binary32 in and out");
+    if (bs && !std::isfinite(view->alpha)) return fail(DR_ERR_INVALID_ARG, "the rate (alpha) must be finite");
     const bool okpair = (in == DR_F32 && out_dtype == DR_F32) || (in == DR_BF16 && out_dtype == DR_F32) ||
                         (in == DR_F64 && out_dtype == DR_F64) || (in == DR_I32 && out_dtype == DR_I32) ||
                         (in == DR_I32 && out_dtype == DR_I64);
     if (!okpair) return fail(DR_ERR_UNSUPPORTED, "for_each %d -> %d is not supported", in, (int)out_dtype);
     Prepared p;
     int items;
-    s = prepare(table, DR_ALGO_FOR_EACH, in, out_dtype, view->arity, 1, tuning, ws, ws_bytes, false, true, p,
-                items);
+    s = prepare(table, DR_ALGO_FOR_EACH, in, out_dtype, view->arity, bs ? 2 : 1, tuning, ws, ws_bytes, false,
+                !bs, p, items);
     if (s) return s;
-    LaunchFn fn = find_for_each(in, out_dtype, view->op, items);
+    LaunchFn fn = bs ? find_black_scholes(items) : find_for_each(in, out_dtype, view->op, items);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "for_each kernel not built for items_per_thread %d", items);
     p.a.alpha = view->alpha;
     return launch(fn, p, stream, "for_each launch");

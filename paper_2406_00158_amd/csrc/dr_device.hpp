@@ -366,6 +366,8 @@ __device__ __forceinline__ uint32_t begin_launch(const uint8_t* ws) {
 struct SegInfo {
     const void* in0;
     const void* in1;
+    const void* in2;
+    const void* in3;
     void* out0;
     void* out1;
     int64_t n;        // length
@@ -400,11 +402,13 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// The fields of a table row that the kernels use, read one by one (ops
-// have arity <= 2 and at most 2 outputs).
+// The fields of a table row that the kernels use, read one by one (zips of
+// at most 4 inputs and at most 2 outputs).
 struct Row {
     const void* in0;
     const void* in1;
+    const void* in2;
+    const void* in3;
     void* out0;
     void* out1;
     int64_t n;
@@ -415,6 +419,8 @@ __device__ __forceinline__ Row load_row(const dr_segment* rows, int64_t k) {
     Row r;
     r.in0 = ld_const(&p->in[0]);
     r.in1 = ld_const(&p->in[1]);
+    r.in2 = ld_const(&p->in[2]);
+    r.in3 = ld_const(&p->in[3]);
     r.out0 = ld_const(&p->out[0]);
     r.out1 = ld_const(&p->out[1]);
     r.n = ld_const(&p->length);
@@ -433,6 +439,8 @@ __device__ __forceinline__ int32_t row_vec_ok(const Row& r, int32_t shift, int a
     const uintptr_t j0 = (uintptr_t)((V - shift) % V);
     bool ok = aligned_at(r.in0, j0, ies);
     if (arity > 1) ok = ok && aligned_at(r.in1, j0, ies);
+    if (arity > 2) ok = ok && aligned_at(r.in2, j0, ies);
+    if (arity > 3) ok = ok && aligned_at(r.in3, j0, ies);
     if (nout > 0) ok = ok && aligned_at(r.out0, j0, oes);
     if (nout > 1) ok = ok && aligned_at(r.out1, j0, oes);
     return ok ? 1 : 0;
@@ -447,6 +455,8 @@ __device__ __forceinline__ bool row_bad(const Row& r, int arity, int nout) {
     if (r.n == 0) return false;
     if (r.in0 == nullptr) return true;
     if (arity > 1 && r.in1 == nullptr) return true;
+    if (arity > 2 && r.in2 == nullptr) return true;
+    if (arity > 3 && r.in3 == nullptr) return true;
     if (nout > 0 && r.out0 == nullptr) return true;
     if (nout > 1 && r.out1 == nullptr) return true;
     return false;
@@ -547,6 +557,8 @@ struct TileMap {
         const Row r = load_row(a.rows, k);
         si.in0 = r.in0;
         si.in1 = r.in1;
+        si.in2 = r.in2;
+        si.in3 = r.in3;
         si.out0 = r.out0;
         si.out1 = r.out1;
         return true;

@@ -110,6 +110,7 @@ LaunchFn find_scan_minmax(int in_dt, int out_dt);
 LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items);
 LaunchFn find_scan_reduce(int in_dt, int reduce_op, int acc, int items);
 LaunchFn find_broadcast_mul(int in_dt, int op, int items);
+LaunchFn find_black_scholes(int items);
 hipError_t launch_plan(const LaunchArgs& a, hipStream_t stream);     // prefix + tile -> segment map
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);  // fill with 0 (graph safe)
 

@@ -190,3 +190,24 @@ def test_batch_10000_ranges_forward_backward():
     wy = np.concatenate(O.reduce_grad(I.split(t["x"], L), I.split(t["y"], L), O.F32, O.MUL, dev_to_np(g), 1,
                                       mode=O.BATCH))
     assert np.array_equal(dev_to_np(gy), wy.astype(np.float32))
+
+
+def test_black_scholes_2_28_options_sampled():
+    """All 2^28 options priced in the default launch; a seeded sample of one
+    million is checked against the oracle (elementwise, so sampled
+    options are checked exactly as the whole would be)."""
+    t = I.options()
+    L = t["lengths"]
+    announce("black-scholes 2^28")
+    ins = [_to_dev(t[n]) for n in ("S", "K", "T", "V")]
+    call, put = torch.empty_like(ins[0]), torch.empty_like(ins[0])
+    B.dr_for_each(B.segments([_pieces(a, L) for a in ins], [_pieces(call, L), _pieces(put, L)]),
+                  B.make_view("black_scholes", B.DR_F32, t["r"]), B.DR_F32)
+    idx = np.sort(np.random.default_rng(5).choice(sum(L), size=1 << 20, replace=False))
+    wc, wp = O.black_scholes(*([t[n][idx]] for n in ("S", "K", "T", "V")), t["r"])
+    gc, gp = dev_to_np(call)[idx].astype(np.float64), dev_to_np(put)[idx].astype(np.float64)
+    scale = t["S"][idx].astype(np.float64) + t["K"][idx].astype(np.float64)
+    ec, ep = np.abs(gc - wc[0]) / scale, np.abs(gp - wp[0]) / scale
+    print(f"black-scholes 2^28: max |err| / (S + K) call {ec.max() / U32:.2f} u32, put {ep.max() / U32:.2f} u32")
+    assert np.all(ec <= 32 * U32) and np.all(ep <= 32 * U32)
+    assert np.all(np.isfinite(dev_to_np(call))) and np.all(np.isfinite(dev_to_np(put)))
