@@ -43,20 +43,27 @@ template <> __device__ __forceinline__ float decode<DR_F32>(float v) { return v;
 template <> __device__ __forceinline__ float decode<DR_BF16>(uint16_t v) { return bf16_decode(v); }
 template <> __device__ __forceinline__ double decode<DR_F64>(double v) { return v; }
 
-// 16-byte vector of V elements, accessed as 4 dwords.
+// Vector of V elements (16 bytes by default; 8 bytes where a kernel wants
+// narrower loads), accessed as one 4- or 2-dword load.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-template <int DT>
+template <int NB> struct vbits;
+template <> struct vbits<16> { using T = u32x4; };
+template <> struct vbits<8> { using T = u32x2; };
+
+template <int DT, int V = vwidth<DT>()>
 struct vec {
-    typename elem<DT>::T e[vwidth<DT>()];
+    typename elem<DT>::T e[V];
 };
 
-template <int DT>
-__device__ __forceinline__ vec<DT> load_vec(const void* base, int64_t j) {
-    const u32x4* p = (const u32x4*)((const char*)base + j * esize<DT>());
-    u32x4 w = __builtin_nontemporal_load(p);
-    vec<DT> v;
-    __builtin_memcpy(&v, &w, 16);
+template <int DT, int V = vwidth<DT>()>
+__device__ __forceinline__ vec<DT, V> load_vec(const void* base, int64_t j) {
+    using R = typename vbits<V * esize<DT>()>::T;
+    const R* p = (const R*)((const char*)base + j * esize<DT>());
+    R w = __builtin_nontemporal_load(p);
+    vec<DT, V> v;
+    __builtin_memcpy(&v, &w, sizeof(R));
     return v;
 }
 
@@ -598,20 +605,20 @@ __device__ __forceinline__ bool tile_full(const SegInfo& si, int64_t u0) {
     return si.vec_ok && j0 >= 0 && j0 + TILE <= si.n;
 }
 
-template <int DT, int SLOTS>
-__device__ __forceinline__ void load_slots(vec<DT> (&x)[SLOTS], const void* base, const SegInfo& si,
+template <int DT, int SLOTS, int V = vwidth<DT>()>
+__device__ __forceinline__ void load_slots(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
                                            int64_t u0, int w, int l, bool rev) {
-    constexpr int V = vwidth<DT>();
+    using R = typename vbits<V * esize<DT>()>::T;
     constexpr int64_t NV = (int64_t)kBlock * SLOTS;
     const int64_t p0 = (int64_t)(w * SLOTS) * 64 + l;
     if (tile_full<V, SLOTS>(si, u0)) {
         const int64_t q0 = rev ? (NV - 1 - p0) : p0;
         const char* b = (const char*)base + (u0 - si.shift + q0 * V) * esize<DT>();
-        const int64_t step = rev ? -64 * 16 : 64 * 16;
+        const int64_t step = rev ? -64 * (int64_t)sizeof(R) : 64 * (int64_t)sizeof(R);
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
-            u32x4 wv = __builtin_nontemporal_load((const u32x4*)(b + s * step));
-            __builtin_memcpy(&x[s], &wv, 16);
+            R wv = __builtin_nontemporal_load((const R*)(b + s * step));
+            __builtin_memcpy(&x[s], &wv, sizeof(R));
         }
         return;
     }
@@ -621,7 +628,7 @@ __device__ __forceinline__ void load_slots(vec<DT> (&x)[SLOTS], const void* base
         const int64_t q = rev ? (NV - 1 - p) : p;
         const int64_t j = u0 + q * V - si.shift;
         if (si.vec_ok && j >= 0 && j + V <= si.n) {
-            x[s] = load_vec<DT>(base, j);
+            x[s] = load_vec<DT, V>(base, j);
         } else {
 #pragma unroll
             for (int e = 0; e < V; ++e) {

@@ -226,12 +226,11 @@ __device__ __forceinline__ double fused_partial(const vec<IDT> (&x)[SLOTS], cons
 // (si, u0, full): the tile's geometry. Elements outside the segment (only
 // in tiles that are not full) were loaded as 0: the identity of a sum, and
 // replaced by the operator's identity otherwise.
-template <int IDT, int OP, bool ZIP, int SLOTS, bool REV, int CMB = kCmbSum>
-__device__ __forceinline__ local_t<IDT> tile_values(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS],
-                                                    local_t<IDT> alpha, local_t<IDT> (&v)[SLOTS][vwidth<IDT>()],
+template <int IDT, int OP, bool ZIP, int SLOTS, bool REV, int CMB = kCmbSum, int V = vwidth<IDT>()>
+__device__ __forceinline__ local_t<IDT> tile_values(const vec<IDT, V> (&x)[SLOTS], const vec<IDT, V> (&y)[SLOTS],
+                                                    local_t<IDT> alpha, local_t<IDT> (&v)[SLOTS][V],
                                                     local_t<IDT> (&base)[SLOTS], bool mn, const SegInfo& si,
                                                     int64_t u0, bool full) {
-    constexpr int V = vwidth<IDT>();
     using L = local_t<IDT>;
     const L id = cmb_id<CMB, L>(mn);
     const int w = threadIdx.x >> 6, l = lane_id();
@@ -260,12 +259,11 @@ __device__ __forceinline__ local_t<IDT> tile_values(const vec<IDT> (&x)[SLOTS], 
 // Outputs of a tile: carry + offset of the wave + prefix inside the wave.
 // `exc`: exclusive scan (each output combines the elements strictly before
 // it in processing order).
-template <int IDT, int ODT, bool C64, int SLOTS, bool REV, int CMB = kCmbSum>
-__device__ __forceinline__ void tile_write(const local_t<IDT> (&v)[SLOTS][vwidth<IDT>()],
+template <int IDT, int ODT, bool C64, int SLOTS, bool REV, int CMB = kCmbSum, int V = vwidth<IDT>()>
+__device__ __forceinline__ void tile_write(const local_t<IDT> (&v)[SLOTS][V],
                                            const local_t<IDT> (&base)[SLOTS], carry_t<IDT, C64> excl,
                                            local_t<IDT> woff, const SegInfo& si, int64_t u0, int w, int l,
                                            bool full, bool exc = false, bool mn = false) {
-    constexpr int V = vwidth<IDT>();
     using L = local_t<IDT>;
     using O = typename elem<ODT>::T;
     const L id = cmb_id<CMB, L>(mn);
@@ -591,7 +589,12 @@ __global__ __launch_bounds__(kScanChunkThreads) void k_scan_chunks(LaunchArgs a)
 
 template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV, int CMB>
 __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
-    constexpr int V = vwidth<IDT>();
+    // int32 -> int64: 8-byte input vectors, so that each lane's outputs are
+    // one 16-byte store and every store instruction of the wave covers
+    // 1 KiB of consecutive memory (4-element vectors would write 32 bytes
+    // per lane as two half-dense stores). The tile and its totals are the
+    // same (integer sums are exact in any order).
+    constexpr int V = (IDT == DR_I32 && ODT == DR_I64) ? 2 : vwidth<IDT>();
     constexpr int SLOTS = ITEMS / V;
     constexpr int WAVES = kBlock / 64;
     constexpr bool ZIP = zip_view<IDT, OP, FUSED, ROP>();
@@ -626,15 +629,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
 
     const int64_t u0 = (t - si.first) * a.tile;
     const bool full = tile_full<V, SLOTS>(si, u0);
-    vec<IDT> x[SLOTS], y[SLOTS];
-    load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, REV);
-    if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, REV);
+    vec<IDT, V> x[SLOTS], y[SLOTS];
+    load_slots<IDT, SLOTS, V>(x, si.in0, si, u0, w, l, REV);
+    if constexpr (ZIP) load_slots<IDT, SLOTS, V>(y, si.in1, si, u0, w, l, REV);
     double rpart_thread = 0.0;
     if constexpr (FUSED) rpart_thread = fused_partial<IDT, ROP, RACC, SLOTS>(x, y);
     const bool mn = (a.flags & kFlagMin) != 0;
     L v[SLOTS][V];
     L base[SLOTS];
-    const L run = tile_values<IDT, OP, ZIP, SLOTS, REV, CMB>(x, y, (L)a.alpha, v, base, mn, si, u0, full);
+    const L run = tile_values<IDT, OP, ZIP, SLOTS, REV, CMB, V>(x, y, (L)a.alpha, v, base, mn, si, u0, full);
     if (l == 0) s_wtot[w] = run;
     if constexpr (FUSED) {
         const double wr = wave_sum(rpart_thread);
@@ -645,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
     for (int i = 0; i < w; ++i) woff = cmb_op<CMB>(woff, s_wtot[i], mn);
     C excl = rh ? from_bits<C>(rc) : cmb_op<CMB>(from_bits<C>(rc), from_bits<C>(ci), mn);
     if (a.flags & kFlagHasInit) excl = cmb_op<CMB>(init_carry<C, IDT>(a), excl, mn);
-    tile_write<IDT, ODT, C64, SLOTS, REV, CMB>(v, base, excl, woff, si, u0, w, l, full,
+    tile_write<IDT, ODT, C64, SLOTS, REV, CMB, V>(v, base, excl, woff, si, u0, w, l, full,
                                                (a.flags & DR_SCAN_EXCLUSIVE) != 0, mn);
     if constexpr (FUSED) {
         if (threadIdx.x >= 64) return;   // wave 0 publishes the partial and combines
