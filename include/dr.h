@@ -272,7 +272,8 @@ dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_
  * (reads the input again, writes the output once); carries are sums in a
  * fixed order, so results repeat from run to run. With
  * DR_TUNE_TILE_PER_BLOCK it is one kernel whose tiles take their carries
- * from a decoupled look-back. Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
+ * from a decoupled look-back; without a tuning, int32 scans of at most 2^22
+ * elements take that form too (lower latency, exact either way). Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
  * (exact modulo 2^32), F32 -> F32 and BF16 -> F32 (binary32 inside a tile,
  * binary64 carries unless DR_SCAN_CARRY_F32), F64 -> F64.
  * In-place (out[0] == in[0], same dtype size) is allowed; other overlap

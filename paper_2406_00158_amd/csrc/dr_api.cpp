@@ -410,6 +410,15 @@ dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_
     return launch(fn, p, stream, "transform_reduce launch");
 }
 
+// Default form of an integer sum scan (no tuning given): up to 2^22
+// elements one kernel with a decoupled look-back has the lower latency (two
+// launches instead of three, about 11 us against 14 us); integer carries are
+// exact either way. Floating-point scans keep the two-pass form at every
+// size: its carries are sums in a fixed order, so results repeat exactly.
+static bool prefer_single_pass(const dr_table* t, int in_dt, const dr_tuning* tu) {
+    return !tu && in_dt == DR_I32 && t && t->total_length <= ((int64_t)1 << 22);
+}
+
 dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t out_dtype, uint32_t flags,
                             void* ws, size_t ws_bytes, const dr_tuning* tuning, void* stream) {
     dr_status s = check_view(view, true);
@@ -432,7 +441,8 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
     p.a.alpha = view->alpha;
     p.a.flags = flags;
-    if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) p.a.flags |= kFlagTilePerBlock;
+    if ((tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) || prefer_single_pass(table, in, tuning))
+        p.a.flags |= kFlagTilePerBlock;
     return launch(fn, p, stream, "inclusive_scan launch");
 }
 
@@ -506,7 +516,8 @@ dr_status dr_scan(const dr_table* table, const dr_view* view, int32_t out_dtype,
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
     p.a.alpha = view->alpha;
     p.a.flags = flags;
-    if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) p.a.flags |= kFlagTilePerBlock;
+    if ((tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) || (!mm && prefer_single_pass(table, in, tuning)))
+        p.a.flags |= kFlagTilePerBlock;
     if (combine == DR_COMBINE_MIN) p.a.flags |= kFlagMin;
     if (init) {
         p.a.flags |= kFlagHasInit;

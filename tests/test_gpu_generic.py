@@ -62,7 +62,7 @@ def test_sum_scan_exclusive_with_init(seg_name, lengths, in_dt, out_dt, mode, re
     init = _init(in_dt, True)
     outs = empty_like_segments(lengths, B.TORCH_DTYPE[out_dt])
     tab = B.segments([place(x, lengths, "separate")], [outs], mode=mode)
-    tu = B.make_tuning(16, B.DR_TUNE_TILE_PER_BLOCK) if form == "look_back" else None
+    tu = B.make_tuning(16, B.DR_TUNE_TILE_PER_BLOCK if form == "look_back" else 0)
     flags = B.DR_SCAN_EXCLUSIVE | (B.DR_SCAN_REVERSE if reverse else 0)
     B.dr_scan(tab, B.make_view("identity", in_dt), out_dt, B.DR_COMBINE_SUM, flags, init, tuning=tu)
     omode = O.BATCH if mode == "batch" else O.CONCAT

@@ -184,13 +184,17 @@ SCAN_CASES = [(B.DR_I32, B.DR_I64), (B.DR_I32, B.DR_I32), (B.DR_F32, B.DR_F32), 
               (B.DR_F64, B.DR_F64)]
 
 
-# the default reduce-then-scan passes, and the single-pass form (one
-# workgroup per tile in block-index order, decoupled look-back)
-SCAN_FORMS = ["two_pass", "look_back"]
+# the library's default (no tuning: the two passes, or for small int32 scans
+# the single pass), the reduce-then-scan passes requested explicitly, and the
+# single-pass form (one workgroup per tile in block-index order, decoupled
+# look-back)
+SCAN_FORMS = ["default", "two_pass", "look_back"]
 
 
 def _scan_tuning(form, items=16):
-    return B.make_tuning(items, B.DR_TUNE_TILE_PER_BLOCK) if form == "look_back" else None
+    if form == "default":
+        return None
+    return B.make_tuning(items, B.DR_TUNE_TILE_PER_BLOCK if form == "look_back" else 0)
 
 
 @pytest.mark.parametrize("seg_name,lengths", SEGMENTATIONS)
