@@ -81,9 +81,8 @@ def test_graph_capture_and_replay():
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(res, ref_r), f"replay {rep}: dot differs from eager"
-        ref = ref_s.double()
-        tol = 1e-5 * (ref.abs() + torch.cumsum(x.double().abs(), 0).max())
-        assert torch.all((s.double() - ref).abs() <= tol), f"replay {rep}: scan differs from eager"
+        # the carries are sums in a fixed order: the replay repeats the eager bits
+        assert torch.equal(s, ref_s), f"replay {rep}: scan differs from eager"
         # eager work between replays, through the same workspace
         _run(tab, res, ws)
         torch.cuda.synchronize()
