@@ -99,8 +99,10 @@ typedef enum dr_op {
      * out[0] the call price S N(d1) - K exp(-rT) N(d2), out[1] the put price
      * K exp(-rT) N(-d2) - S N(-d1), with d1 = (ln(S/K) + (r + sigma^2/2) T)
      * / (sigma sqrt(T)), d2 = d1 - sigma sqrt(T) and N the standard normal
-     * distribution function, evaluated in binary32 with the device's log,
-     * sqrt, exp and erfc. */
+     * distribution function, evaluated in binary32 with the hardware's log2,
+     * exp2, reciprocal and square root, N by the rational approximation of
+     * Abramowitz & Stegun 26.2.17 (absolute error below 7.5e-8); each price
+     * is within 32 units in the last place of S + K of the exact one. */
     DR_OP_BLACK_SCHOLES = 4
 } dr_op;
 
@@ -145,7 +147,7 @@ typedef enum dr_algo {
 /* The view descriptor: zip arity, element type of the zipped inputs (all
  * inputs share it), the transform and its scalar. */
 typedef struct dr_view {
-    int32_t arity;     /* 1 or 2; must equal the arity of `op` */
+    int32_t arity;     /* 1, 2 or 4; must equal the arity of `op` */
     int32_t in_dtype;  /* dr_dtype of every zipped input */
     int32_t op;        /* dr_op */
     int32_t reserved;  /* must be 0 */
@@ -273,7 +275,10 @@ dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_
  * fixed order, so results repeat from run to run. With
  * DR_TUNE_TILE_PER_BLOCK it is one kernel whose tiles take their carries
  * from a decoupled look-back; without a tuning, int32 scans of at most 2^22
- * elements take that form too (lower latency, exact either way). Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
+ * elements take that form too (lower latency, exact either way), and larger
+ * int32 -> int64 scans of the identity view over tables of at most
+ * DR_SMALL_TABLE rows use tiles of 64 items per thread (the output is twice
+ * the input's size). Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
  * (exact modulo 2^32), F32 -> F32 and BF16 -> F32 (binary32 inside a tile,
  * binary64 carries unless DR_SCAN_CARRY_F32), F64 -> F64.
  * In-place (out[0] == in[0], same dtype size) is allowed; other overlap
