@@ -108,7 +108,9 @@ typedef enum dr_op {
 
 /* Floating-point accumulation of a reduction. PLAIN: binary32 sums inside a
  * tile. COMPENSATED: binary32 (sum, error) pairs with error-free
- * transformations (TwoSum, FMA-based TwoProduct) inside a tile. In both, the
+ * transformations (TwoSum, FMA-based TwoProduct) inside a tile; bfloat16
+ * values, squares and products, which are exact in binary32, are summed in
+ * binary64 instead (fewer operations, at least as accurate). In both, the
  * tile partials and the combine across tiles and segments are binary64.
  * Integer reductions are always exact in int64 and ignore this setting.
  * binary64 inputs always accumulate in binary64. */
@@ -182,7 +184,9 @@ typedef struct dr_table {
 /* Launch shape. block_threads: 256 (the only shape built in this version);
  * items_per_thread: elements per thread per tile, one of the values
  * dr_tuning_supported accepts; flags: DR_TUNE_* bits. NULL = the built-in
- * default for the call. */
+ * default for the call: 16 items per thread, except bfloat16 reductions (32)
+ * and the scan defaults described at dr_inclusive_scan. dr_plan and
+ * dr_workspace_bytes given NULL assume the same defaults. */
 typedef struct dr_tuning {
     int32_t block_threads;
     int32_t items_per_thread;
@@ -340,7 +344,8 @@ enum { DR_SCAN_EXCLUSIVE = 4 };
  * +inf / INT64_MAX for min); an empty range gives it. DR_COMBINE_SUM is
  * dr_transform_reduce (`acc` as there); for max / min `acc` is ignored and
  * every op and input dtype is supported at the default tile (16 items per
- * thread). Results, workspace and tuning as dr_transform_reduce.
+ * thread; bfloat16 32, and 16 with a tuning). Results, workspace and tuning
+ * as dr_transform_reduce.
  */
 dr_status dr_reduce(const dr_table* table, const dr_view* view, int32_t combine, int32_t acc,
                     const void* init, void* result, void* workspace, size_t ws_bytes,

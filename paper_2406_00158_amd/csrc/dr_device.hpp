@@ -284,6 +284,41 @@ __device__ __forceinline__ void comp_accumulate(const vec<IDT> (&x)[SLOTS], cons
     }
 }
 
+// The compensated sum of the view over a thread's elements, as binary64.
+// bfloat16 values, squares and products are exact in binary32 (at most 16
+// significant bits), so they are summed in binary64 instead of in TwoSum
+// pairs: two operations per element instead of TwoSum's six, and the sum is
+// exact until it needs more than 53 significant bits. Two accumulators (even
+// and odd elements) shorten the dependency chain; the order is fixed.
+// Otherwise the (sum, error) pair of comp_accumulate, joined in binary64
+// (exactly, unless the sum is not finite).
+template <int IDT, int OP, int SLOTS>
+__device__ __forceinline__ double comp_partial(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS], float alpha) {
+    constexpr int V = vwidth<IDT>();
+    if constexpr (IDT == DR_BF16 && (OP == DR_OP_IDENTITY || OP == DR_OP_SQUARE || OP == DR_OP_MUL)) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const float x0 = decode<IDT>(x[q].e[e]);
+                float p;
+                if constexpr (OP == DR_OP_IDENTITY) p = x0;
+                else if constexpr (OP == DR_OP_SQUARE) p = x0 * x0;
+                else p = x0 * decode<IDT>(y[q].e[e]);
+                if (e & 1) s1 += (double)p;
+                else s0 += (double)p;
+            }
+        }
+        (void)alpha;
+        return s0 + s1;
+    } else {
+        float s = 0.0f, c = 0.0f;
+        comp_accumulate<IDT, OP, SLOTS>(x, y, alpha, s, c);
+        return __builtin_isfinite(s) ? (double)s + (double)c : (double)s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Cross-workgroup status words
 // ---------------------------------------------------------------------------

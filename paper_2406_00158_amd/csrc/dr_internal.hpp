@@ -105,7 +105,7 @@ hipError_t launch_prologue(const LaunchArgs& a, hipStream_t stream);
 // returns nullptr when the combination is not built.
 LaunchFn find_for_each(int in_dt, int out_dt, int op, int items);
 LaunchFn find_reduce(int in_dt, int op, int acc, int items);
-LaunchFn find_reduce_minmax(int in_dt, int op);
+LaunchFn find_reduce_minmax(int in_dt, int op, int items);
 LaunchFn find_scan_minmax(int in_dt, int out_dt);
 LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items);
 LaunchFn find_scan_reduce(int in_dt, int reduce_op, int acc, int items);

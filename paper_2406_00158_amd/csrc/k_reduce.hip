@@ -100,10 +100,7 @@ __device__ __forceinline__ partial_t<IDT> tile_partial(const LaunchArgs& a, cons
             for (int i = 0; i < WAVES; ++i) part = mm_op(part, s_wave[i], mn);
         }
     } else if constexpr (F32PATH && ACC == DR_ACC_COMPENSATED) {
-        float s = 0.0f, c = 0.0f;
-        comp_accumulate<IDT, OP, SLOTS>(x, y, (float)a.alpha, s, c);
-        P tp = (double)s + (double)c;   // exact unless s is not finite
-        if (!__builtin_isfinite(s)) tp = (double)s;
+        const P tp = comp_partial<IDT, OP, SLOTS>(x, y, (float)a.alpha);
         const P wsum = wave_sum(tp);
         if (l == 0) s_wave[w] = wsum;
         __syncthreads();
@@ -186,9 +183,7 @@ __device__ __forceinline__ partial_t<IDT> thread_tile_sum(const vec<IDT> (&x)[SL
     constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
     using P = partial_t<IDT>;
     if constexpr ((IDT == DR_F32 || IDT == DR_BF16) && ACC == DR_ACC_COMPENSATED) {
-        float s = 0.0f, c = 0.0f;
-        comp_accumulate<IDT, OP, SLOTS>(x, y, (float)alpha_d, s, c);
-        return __builtin_isfinite(s) ? (double)s + (double)c : (double)s;
+        return comp_partial<IDT, OP, SLOTS>(x, y, (float)alpha_d);
     } else if constexpr (IDT == DR_F32 || IDT == DR_BF16) {
         const float alpha = (float)alpha_d;
         float acc = 0.0f;
@@ -310,11 +305,12 @@ hipError_t launch_reduce(const LaunchArgs& a, int64_t grid, hipStream_t stream) 
         }                                                                             \
     }
 
-// max / min reductions (every op, 16 items).
-LaunchFn find_reduce_minmax(int in_dt, int op) {
-    const int items = 16, acc = kAccMinMax;
+// max / min reductions (every op, 16 items; bfloat16 also 32, its default).
+LaunchFn find_reduce_minmax(int in_dt, int op, int items) {
+    const int acc = kAccMinMax;
     if (in_dt == DR_F32) { DR_RED_OPS(DR_F32, kAccMinMax, 16) }
     if (in_dt == DR_BF16) { DR_RED_OPS(DR_BF16, kAccMinMax, 16) }
+    if (in_dt == DR_BF16) { DR_RED_OPS(DR_BF16, kAccMinMax, 32) }
     if (in_dt == DR_F64) { DR_RED_OPS(DR_F64, kAccMinMax, 16) }
     if (in_dt == DR_I32) { DR_RED_OPS(DR_I32, kAccMinMax, 16) }
     return nullptr;

@@ -204,18 +204,18 @@ __device__ __forceinline__ double fused_partial(const vec<IDT> (&x)[SLOTS], cons
         }
         return rs;
     } else {
-        float rs = 0.0f, rc = 0.0f;
         if constexpr (RACC == DR_ACC_COMPENSATED) {
-            comp_accumulate<IDT, ROP, SLOTS>(x, y, 0.0f, rs, rc);
+            return comp_partial<IDT, ROP, SLOTS>(x, y, 0.0f);
         } else {
+            float rs = 0.0f;
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
 #pragma unroll
                 for (int e = 0; e < V; ++e)
                     rs += view_apply<ROP, float>((float)decode<IDT>(x[s].e[e]), (float)decode<IDT>(y[s].e[e]), 0.0f);
             }
+            return (double)rs;
         }
-        return (double)rs + (double)rc;
     }
 }
 
