@@ -256,9 +256,10 @@ class Workspace:
                                        tptr, ctypes.byref(size)))
         self.ensure(size.value)
         if table.n_segments > DR_SMALL_TABLE:
+            # a plan is built for one tile size: the algorithm and the tuning
+            # fix it (the defaults differ between algorithms and dtypes)
             items = tuning.items_per_thread if tuning is not None else 0
-            key = (table.dev_rows.data_ptr(), table.n_segments, table.total_length, view.in_dtype,
-                   algo if algo == DR_ALGO_SCAN_REDUCE else -1, items)
+            key = (table.dev_rows.data_ptr(), table.n_segments, table.total_length, view.in_dtype, algo, items)
             if key != self.plan_key:
                 c = table.c_table(host_check=False)
                 check(lib().dr_plan(ctypes.byref(c), algo, ctypes.byref(view), tptr, self.ptr,

@@ -15,7 +15,7 @@ from paper_2406_00158_amd import binding as B
 from paper_2406_00158_amd import inputs as I
 
 from gpu_util import (U32, U64, announce, dev, dev_to_np, empty_like_segments, gather, np_to_dev, place,
-                      reduce_bound, scan_fp32_bound)
+                      reduce_bound, scan_fp32_bound, separate)
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -391,3 +391,30 @@ def test_scan_malformed_row_of_planned_table_is_flagged(form):
                         tuning=_scan_tuning(form))
     assert np.array_equal(dev_to_np(out), np.arange(1, 13001, dtype=np.float32))
     assert ws.device_status() == 0
+
+
+def test_one_workspace_across_algorithms_with_different_default_tiles():
+    """A large (planned) bfloat16 table used by a reduction (default 32 items
+    per thread), then a for_each and a scan (16), then the reduction again,
+    all through one workspace: each call must run on a plan of its own tile
+    size (a stale plan would be flagged and the call skipped)."""
+    announce("plan per algorithm")
+    lengths = [(k * 61) % 900 + 1 for k in range(150)]
+    n = sum(lengths)
+    xb = I.bf16_bits(I.normal_f32(n, 17))
+    ins = separate(xb, lengths)
+    outs = empty_like_segments(lengths, torch.float32)
+    ws = B.Workspace(dev())
+    v = B.make_view("square", B.DR_BF16)
+    want_sq, mag = O.reduce([xb], None, O.BF16, O.SQUARE)
+    for rep in range(2):
+        r = torch.zeros(1, dtype=torch.float64, device=dev())
+        B.dr_transform_reduce(B.segments([ins]), v, B.DR_ACC_COMPENSATED, 0.0, r, workspace=ws)
+        assert abs(r.item() - want_sq[0]) <= reduce_bound(mag[0], "compensated", items=32, tiles=n // 8192 + 150)
+        B.dr_for_each(B.segments([ins], [outs]), v, B.DR_F32, workspace=ws)
+        assert np.array_equal(gather(outs), O.for_each([xb], None, O.BF16, O.SQUARE, O.F32)[0])
+        B.dr_inclusive_scan(B.segments([ins], [outs]), B.make_view("identity", B.DR_BF16), B.DR_F32, workspace=ws)
+        ref, absp = O.scan([xb], None, O.BF16, O.IDENTITY, want_abs=True)
+        got = gather(outs).astype(np.float64)
+        assert np.all(np.abs(got - ref[0]) <= scan_fp32_bound(ref[0], absp[0], elem_bytes=2, tiles=n // 4096 + 150))
+        assert ws.device_status() == 0, f"round {rep}: a call ran on a stale plan"
