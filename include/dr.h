@@ -202,6 +202,20 @@ typedef struct dr_tuning {
  * the default read-only tile-totals pass followed by the apply pass. */
 enum { DR_TUNE_TILE_PER_BLOCK = 1 };
 
+/* dr_tuning.flags for inclusive_scan, scan (sum) and scan_reduce: one pass
+ * whose workgroups, one per CU and all resident (a cooperative launch),
+ * split their waves into loaders (the input into a ring of LDS slots and
+ * each tile's total), writers (tile scan plus carry, outputs written once),
+ * a publisher of the totals and a fetcher of the carries, while one
+ * workgroup scans the published totals in a fixed order (results repeat
+ * from run to run). Built for sums of the identity view over binary32,
+ * bfloat16, binary64 and int32 -> int32 (fused: binary32), at 32 items per
+ * thread (binary64 and fused 16), which items_per_thread must name. Where
+ * the device cannot hold the whole grid at once, or the stream is being
+ * captured into a graph, the call runs the default two passes instead.
+ * Results are those of a fixed order of operations, like the default's. */
+enum { DR_TUNE_SPECIALIZED = 2 };
+
 /* Library version (DR_ABI_VERSION). Never fails. */
 int dr_abi_version(void);
 

@@ -174,7 +174,8 @@ dr_status check_host_rows(const dr_table* t, int arity, int nout, int ies, int o
 dr_status resolve_items(const dr_tuning* tu, int algo, int in_dt, int& items) {
     items = default_items(algo, in_dt);
     if (!tu) return DR_OK;
-    if ((tu->flags & ~DR_TUNE_TILE_PER_BLOCK) || tu->reserved) return fail(DR_ERR_INVALID_ARG, "unknown tuning bits");
+    if ((tu->flags & ~(DR_TUNE_TILE_PER_BLOCK | DR_TUNE_SPECIALIZED)) || tu->reserved)
+        return fail(DR_ERR_INVALID_ARG, "unknown tuning bits");
     if (tu->block_threads != 0 && tu->block_threads != kBlock)
         return fail(DR_ERR_UNSUPPORTED, "block_threads must be %d", kBlock);
     if (tu->items_per_thread != 0) items = tu->items_per_thread;
@@ -420,6 +421,40 @@ static bool prefer_single_pass(const dr_table* t, int in_dt, const dr_tuning* tu
     return !tu && in_dt == DR_I32 && t && t->total_length <= ((int64_t)1 << 22);
 }
 
+// The single pass with specialised waves, on request (DR_TUNE_SPECIALIZED,
+// at the form's own tile size). It is not the default: at 2^28 binary32
+// elements it measured 557 us against 509 us for the two passes (the
+// loaders' partial-tile path makes the compiler wait for every load in
+// flight before each tile, and the fused form's combine runs in the wave
+// that publishes the totals). On success `use` is the tuning to prepare
+// with and `on` says whether the form runs.
+static dr_status specialized_tuning(const dr_table* t, int in_dt, int out_dt, int op, bool fused, bool c64,
+                                    int acc, const dr_tuning* tu, dr_tuning& tmp, const dr_tuning*& use,
+                                    bool& on) {
+    use = tu;
+    on = false;
+    const int items = ws_items_for(in_dt, fused);
+    const bool built = op == DR_OP_IDENTITY && items > 0 && !(in_dt == DR_I32 && out_dt == DR_I64) &&
+                       (fused ? find_scan_reduce(in_dt, DR_OP_MUL, acc, items) != nullptr
+                              : find_scan(in_dt, out_dt, op, c64, items) != nullptr);
+    if (tu && (tu->flags & DR_TUNE_SPECIALIZED)) {
+        if (tu->flags & DR_TUNE_TILE_PER_BLOCK)
+            return fail(DR_ERR_INVALID_ARG, "DR_TUNE_SPECIALIZED and DR_TUNE_TILE_PER_BLOCK exclude each other");
+        if (!built)
+            return fail(DR_ERR_UNSUPPORTED, "the specialised-wave scan is built for sums of the identity view "
+                                            "(binary32, bfloat16, binary64, int32 -> int32; fused: binary32)");
+        if (tu->items_per_thread != items)
+            return fail(DR_ERR_UNSUPPORTED, "the specialised-wave scan of this dtype is built for %d items per thread",
+                        items);
+        tmp = *tu;
+        use = &tmp;
+        on = true;
+        return DR_OK;
+    }
+    (void)t;
+    return DR_OK;
+}
+
 // Without a tuning, int32 -> int64 sums of the identity view over more than
 // 2^22 elements use tiles of 64 items per thread: the apply pass writes
 // twice the bytes it reads, and larger tiles were measured 6 % faster at
@@ -451,16 +486,22 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
         return fail(DR_ERR_INVALID_ARG, "DR_SCAN_CARRY_F32 applies to binary32/bfloat16 inputs only");
     Prepared p;
     int items;
-    dr_tuning dflt;
+    dr_tuning dflt, wst;
+    const dr_tuning* wsu = nullptr;
+    bool ws_on = false;
+    s = specialized_tuning(table, in, out_dtype, view->op, false, (flags & DR_SCAN_CARRY_F32) == 0, 0, tuning, wst,
+                           wsu, ws_on);
+    if (s) return s;
     s = prepare(table, DR_ALGO_SCAN, in, out_dtype, view->arity, 1,
-                scan_tuning(table, in, out_dtype, view->op, tuning, dflt), ws, ws_bytes, true,
+                ws_on ? wsu : scan_tuning(table, in, out_dtype, view->op, tuning, dflt), ws, ws_bytes, true,
                 view->op == DR_OP_IDENTITY, p, items);
     if (s) return s;
     LaunchFn fn = find_scan(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
     p.a.alpha = view->alpha;
     p.a.flags = flags;
-    if ((tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) || prefer_single_pass(table, in, tuning))
+    if (ws_on) p.a.flags |= kFlagSpecialized;
+    else if ((tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) || prefer_single_pass(table, in, tuning))
         p.a.flags |= kFlagTilePerBlock;
     return launch(fn, p, stream, "inclusive_scan launch");
 }
@@ -525,19 +566,29 @@ dr_status dr_scan(const dr_table* table, const dr_view* view, int32_t out_dtype,
         if (tuning && tuning->items_per_thread != 0 && tuning->items_per_thread != 16)
             return fail(DR_ERR_UNSUPPORTED, "max / min scans are built for 16 items per thread");
     }
+    if (mm && tuning && (tuning->flags & DR_TUNE_SPECIALIZED))
+        return fail(DR_ERR_UNSUPPORTED, "max / min scans run in the reduce-then-scan form only");
     Prepared p;
     int items;
-    dr_tuning dflt;
+    dr_tuning dflt, wst;
+    const dr_tuning* wsu = nullptr;
+    bool ws_on = false;
+    if (!mm) {
+        s = specialized_tuning(table, in, out_dtype, view->op, false, (flags & DR_SCAN_CARRY_F32) == 0, 0, tuning,
+                               wst, wsu, ws_on);
+        if (s) return s;
+    }
     s = prepare(table, DR_ALGO_SCAN, in, out_dtype, view->arity, 1,
-                mm ? tuning : scan_tuning(table, in, out_dtype, view->op, tuning, dflt), ws, ws_bytes, true,
-                view->op == DR_OP_IDENTITY, p, items);
+                mm ? tuning : ws_on ? wsu : scan_tuning(table, in, out_dtype, view->op, tuning, dflt), ws, ws_bytes,
+                true, view->op == DR_OP_IDENTITY, p, items);
     if (s) return s;
     LaunchFn fn = mm ? find_scan_minmax(in, out_dtype)
                      : find_scan(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
     p.a.alpha = view->alpha;
     p.a.flags = flags;
-    if ((tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) || (!mm && prefer_single_pass(table, in, tuning)))
+    if (ws_on) p.a.flags |= kFlagSpecialized;
+    else if ((tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) || (!mm && prefer_single_pass(table, in, tuning)))
         p.a.flags |= kFlagTilePerBlock;
     if (combine == DR_COMBINE_MIN) p.a.flags |= kFlagMin;
     if (init) {
@@ -568,12 +619,18 @@ dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view, const 
         return fail(DR_ERR_INVALID_ARG, "result is NULL");
     Prepared p;
     int items;
-    s = prepare(table, DR_ALGO_SCAN_REDUCE, in, in, 2, 1, tuning, ws, ws_bytes, true, true, p, items);
+    dr_tuning wst;
+    const dr_tuning* wsu = nullptr;
+    bool ws_on = false;
+    s = specialized_tuning(table, in, in, DR_OP_IDENTITY, true, true, acc, tuning, wst, wsu, ws_on);
+    if (s) return s;
+    s = prepare(table, DR_ALGO_SCAN_REDUCE, in, in, 2, 1, ws_on ? wsu : tuning, ws, ws_bytes, true, true, p, items);
     if (s) return s;
     LaunchFn fn = find_scan_reduce(in, reduce_view->op, acc, items);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "fused scan kernel not built for this combination");
     p.a.flags = flags;
-    if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) p.a.flags |= kFlagTilePerBlock;
+    if (ws_on) p.a.flags |= kFlagSpecialized;
+    else if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) p.a.flags |= kFlagTilePerBlock;
     p.a.result = result;
     p.a.init_f = *(const double*)init;
     return launch(fn, p, stream, "scan_reduce launch");

@@ -93,6 +93,11 @@ constexpr uint32_t kFlagTilePerBlock = 1u << 16;
 constexpr uint32_t kFlagHasInit = 1u << 17;   // scans: combine init into every output
 constexpr uint32_t kFlagMin = 1u << 18;       // min/max kernels: min (else max)
 constexpr int kAccMinMax = 2;                 // reduce kernels: max / min instead of a sum
+constexpr uint32_t kFlagSpecialized = 1u << 19;   // scans: the single pass with specialised waves
+
+// Items per thread of the scans' specialised-wave form for an input dtype
+// (0: not built).
+int ws_items_for(int in_dt, bool fused);
 
 // Workgroups of `kernel` (of `threads` threads) that can be resident at once.
 int resident_grid(const void* kernel, int threads = kBlock);

@@ -660,6 +660,442 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-pass form with specialised waves (the default for large scans of
+// tables that need no plan)
+// ---------------------------------------------------------------------------
+//
+// One workgroup per CU, all resident (cooperative launch); workgroup 0 is
+// the carry agent, workgroup 1 + g owns the processing indices g, g + G,
+// g + 2G, ... (G = tile workgroups). Inside a tile workgroup:
+//   waves 0-3  load a tile into registers, form its wave totals exactly as
+//              the output pass will, and copy the raw tile into a ring of
+//              LDS slots (they only ever load: their in-order memory counter
+//              never waits behind a store, so two tiles stay in flight);
+//   waves 4-7  take a tile from the ring with its carry, scan it in
+//              registers and write it (they never wait for a load);
+//   wave 8     publishes each tile's total (and, fused, its dot partial and
+//              the combine) as soon as the loaders have it;
+//   wave 9     fetches the carries of the next ring slots in one round trip.
+// The agent scans the published tile totals in windows of kWsWindow tiles
+// with a fixed shape (a serial pass over each thread's tiles, a wave scan,
+// the waves in order, the window's carry in), so every carry is the same
+// sum at every run, and publishes each tile's inclusive prefix; lanes past
+// the first unpublished total never feed an earlier one, so a window's
+// prefix can be published before the window is complete. Reads: the input
+// once; writes: the output once.
+
+constexpr int kWsWaves = 10;
+constexpr int kWsThreads = 64 * kWsWaves;
+constexpr int kWsAgentWaves = 8;
+constexpr int kWsPerThread = 4;
+constexpr int kWsWindow = kWsPerThread * 64 * kWsAgentWaves;
+constexpr int kWsLdsBytes = 128 * 1024;   // ring budget per workgroup
+
+__device__ __forceinline__ int lds_ld(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(int* p, int v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Bounded wait for an LDS counter; false (and the fault flag) on timeout.
+__device__ __forceinline__ bool ws_wait(const int* p, int target, const LaunchArgs& a) {
+    if (lds_ld(p) >= target) return true;
+    Deadline dl(a.spin_ticks);
+    while (lds_ld(p) < target) {
+        if (dl.passed()) {
+            if (lane_id() == 0) flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+// A tile's published total: words kAggWord, kAggWord + 1 with the launch tag
+// in the upper halves; the tag of the second word has its top bit flipped
+// when the tile starts a range (the segmented scan restarts there).
+constexpr uint32_t kHeadBit = 0x80000000u;
+
+template <class C>
+__device__ __forceinline__ void ws_publish(uint64_t* tw, uint32_t tag, bool head, C total) {
+    const uint64_t v = to_bits(total);
+    atomic_st(tw + kAggWord, ((uint64_t)tag << 32) | (uint32_t)v);
+    atomic_st(tw + kAggWord + 1, ((uint64_t)(head ? tag ^ kHeadBit : tag) << 32) | (uint32_t)(v >> 32));
+}
+
+// The agent: inclusive prefixes of the (head, total) pairs in processing
+// order, written to words kInclWord, kInclWord + 1 of every tile.
+template <class C>
+__device__ void ws_agent(const LaunchArgs& a, uint32_t tag, int64_t T) {
+    __shared__ uint32_t s_zmin[kWsWaves];
+    __shared__ C s_wt[kWsAgentWaves];
+    __shared__ int s_wh[kWsAgentWaves];
+    __shared__ C s_last;
+    __shared__ int s_to;
+    constexpr int PT = kWsPerThread;
+    uint64_t* tws = (uint64_t*)(a.ws + a.lay.off_tile);
+    const int64_t TW = a.lay.tile_words;
+    const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), l = lane_id();
+    C carry = (C)0;
+    for (int64_t base = 0; base < T; base += kWsWindow) {
+        const int n = (int)(T - base < kWsWindow ? T - base : kWsWindow);
+        bool have[PT], hd[PT];
+        C v[PT];
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            have[j] = false;
+            hd[j] = false;
+            v[j] = (C)0;
+        }
+        int pub = 0, nap = 1;
+        Deadline dl(a.spin_ticks);
+        while (true) {
+            uint32_t fm = 0xffffffffu;   // first index of this thread not yet published
+            if (w < kWsAgentWaves) {
+                uint64_t q0[PT], q1[PT];
+#pragma unroll
+                for (int j = 0; j < PT; ++j) {
+                    const int idx = PT * tid + j < n ? PT * tid + j : n - 1;
+                    const uint64_t* p = tws + (base + idx) * TW + kAggWord;
+                    q0[j] = atomic_ld(p);
+                    q1[j] = atomic_ld(p + 1);
+                }
+#pragma unroll
+                for (int j = 0; j < PT; ++j) {
+                    const int idx = PT * tid + j;
+                    const uint32_t t0 = (uint32_t)(q0[j] >> 32), t1 = (uint32_t)(q1[j] >> 32);
+                    if (idx < n && !have[j] && t0 == tag && (t1 == tag || t1 == (tag ^ kHeadBit))) {
+                        have[j] = true;
+                        hd[j] = t1 != tag;
+                        v[j] = from_bits<C>((uint64_t)(uint32_t)q0[j] | ((uint64_t)(uint32_t)q1[j] << 32));
+                    }
+                }
+#pragma unroll
+                for (int j = PT - 1; j >= 0; --j)
+                    if (PT * tid + j < n && !have[j]) fm = (uint32_t)(PT * tid + j);
+            }
+            uint32_t wm = fm;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const uint32_t o = (uint32_t)__shfl_xor((int)wm, d, 64);
+                wm = wm < o ? wm : o;
+            }
+            if (l == 0) s_zmin[w] = wm;
+            // fixed-shape segmented scan of the window; unpublished entries
+            // are the identity and only ever feed later ones
+            C run = (C)0;
+            bool rh = false;
+            C loc[PT];
+            bool loch[PT];
+#pragma unroll
+            for (int j = 0; j < PT; ++j) {
+                const bool hj = have[j] && hd[j];
+                const C vj = have[j] ? v[j] : (C)0;
+                run = hj ? vj : run + vj;
+                rh = rh || hj;
+                loc[j] = run;
+                loch[j] = rh;
+            }
+            C sv = run;
+            int sh = rh ? 1 : 0;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const C pv = __shfl_up(sv, d, 64);
+                const int ph = __shfl_up(sh, d, 64);
+                if (l >= d) {
+                    if (!sh) sv = pv + sv;
+                    sh = sh | ph;
+                }
+            }
+            if (w < kWsAgentWaves && l == 63) {
+                s_wt[w] = sv;
+                s_wh[w] = sh;
+            }
+            C ev = __shfl_up(sv, 1, 64);
+            int eh = __shfl_up(sh, 1, 64);
+            if (l == 0) {
+                ev = (C)0;
+                eh = 0;
+            }
+            __syncthreads();
+            uint32_t z = (uint32_t)n;
+            for (int i = 0; i < kWsWaves; ++i) z = s_zmin[i] < z ? s_zmin[i] : z;
+            C c = carry;
+            for (int i = 0; i < w && i < kWsAgentWaves; ++i) c = s_wh[i] ? s_wt[i] : c + s_wt[i];
+            c = eh ? ev : c + ev;
+            if (w < kWsAgentWaves) {
+#pragma unroll
+                for (int j = 0; j < PT; ++j) {
+                    const int idx = PT * tid + j;
+                    const C I = loch[j] ? loc[j] : c + loc[j];
+                    if (idx >= pub && idx < (int)z) tagged_store(tws + (base + idx) * TW + kInclWord, tag, to_bits(I));
+                    if (idx == n - 1 && (int)z == n) s_last = I;
+                }
+            }
+            if (tid == 0) s_to = ((int)z < n && dl.passed()) ? 1 : 0;
+            __syncthreads();
+            const bool progress = (int)z > pub;
+            pub = (int)z;
+            if ((int)z == n) {
+                carry = s_last;
+                break;
+            }
+            if (s_to) {
+                if (tid == 0) flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
+                return;
+            }
+            if (progress) {
+                nap = 1;
+                dl = Deadline(a.spin_ticks);
+            } else {
+                for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(1);
+                nap = nap < 4 ? 2 * nap : 4;
+            }
+            __syncthreads();   // s_zmin / s_wt are rewritten next round
+        }
+        __syncthreads();
+    }
+}
+
+// Tiles of the specialised-wave form: 32 items per thread (binary64 16), so
+// that every role of the one kernel fits in the registers of three waves
+// per SIMD without spilling; fused, where the loaders hold both inputs, 16. Built for the identity view of each scan
+// dtype pair but int32 -> int64.
+template <int IDT, bool FUSED>
+constexpr int ws_items() {
+    return FUSED ? 16 : (IDT == DR_F64 ? 16 : 32);
+}
+
+template <int IDT, int ODT, int OP, bool FUSED, int ITEMS>
+constexpr bool ws_form() {
+    return OP == DR_OP_IDENTITY && ITEMS == ws_items<IDT, FUSED>() && !(IDT == DR_I32 && ODT == DR_I64) &&
+           (!FUSED || IDT == DR_F32);
+}
+
+int ws_items_for(int in_dt, bool fused) {
+    if (fused) return in_dt == DR_F32 ? 16 : 0;
+    return in_dt == DR_F64 ? 16 : 32;
+}
+
+template <int IDT, int ITEMS, bool FUSED>
+constexpr int ws_ring() {
+    constexpr int bytes = kBlock * ITEMS * esize<IDT>();
+    constexpr int r = kWsLdsBytes / bytes;
+    return r > 4 ? 4 : r;
+}
+
+template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
+__global__ __launch_bounds__(kWsThreads) void k_scan_ws(LaunchArgs a) {
+    constexpr int V = vwidth<IDT>();
+    constexpr int SLOTS = ITEMS / V;
+    constexpr int R = ws_ring<IDT, ITEMS, FUSED>();
+    static_assert(R >= 2, "the ring needs two slots");
+    using L = local_t<IDT>;
+    using C = carry_t<IDT, C64>;
+    __shared__ vec<IDT> s_data[R][kBlock * SLOTS];
+    __shared__ L s_wt[R][4];
+    __shared__ double s_red[R][4];
+    __shared__ int s_ready[R], s_done[R], s_cseq[R];
+    __shared__ C s_carry[R];
+
+    const uint32_t tag = begin_launch(a.ws);
+    TileMap tm;
+    tm.init(a);
+    if (!tm.ok) return;
+    const int64_t T = tm.total_tiles;
+    if (blockIdx.x == 0) {
+        if (FUSED && T == 0 && threadIdx.x == 0) {   // no tiles at all
+            if (a.mode == DR_MODE_BATCH) write_all_init<double>(a);
+            else write_result<double>(a, 0, 0.0);
+        }
+        ws_agent<C>(a, tag, T);
+        return;
+    }
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int l = lane_id();
+    const int64_t G = gridDim.x - 1;
+    const int64_t g = blockIdx.x - 1;
+    const int64_t K = g < T ? (T - 1 - g) / G + 1 : 0;   // tiles of this workgroup
+    if (threadIdx.x < R) {
+        s_ready[threadIdx.x] = 0;
+        s_done[threadIdx.x] = 0;
+        s_cseq[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    if (K == 0) return;
+    uint64_t* tws = (uint64_t*)(a.ws + a.lay.off_tile);
+    const int64_t TW = a.lay.tile_words;
+    auto proc = [&](int64_t k) { return g + k * G; };                 // processing index
+    auto phys = [&](int64_t r) { return REV ? T - 1 - r : r; };        // physical tile
+    const L alpha = (L)a.alpha;
+
+    if (w < 4) {
+        // loaders: two tiles in flight in registers, then into the ring
+        vec<IDT> xa[SLOTS], xb[SLOTS], ya[SLOTS], yb[SLOTS];
+        SegInfo sa, sb;
+        bool oka = false, okb = false;
+        auto issue = [&](int64_t k, SegInfo& si, vec<IDT> (&x)[SLOTS], vec<IDT> (&y)[SLOTS]) -> bool {
+            const int64_t r = proc(k < K ? k : K - 1);
+            const int64_t t = phys(r);
+            if (!tm.find(a, t, si)) return false;
+            const int64_t u0 = (t - si.first) * a.tile;
+            load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, REV);
+            if constexpr (FUSED) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, REV);
+            return true;
+        };
+        auto stage = [&](int64_t k, bool ok, const SegInfo& si, const vec<IDT> (&x)[SLOTS],
+                         const vec<IDT> (&y)[SLOTS]) -> bool {
+            const int slot = (int)(k % R);
+            const int fill = (int)(k / R);
+            L run = (L)0;
+            double part = 0.0;
+            if (ok) {
+                const int64_t u0 = (phys(proc(k)) - si.first) * a.tile;
+                L v[SLOTS][V];
+                L base[SLOTS];
+                run = tile_values<IDT, OP, false, SLOTS, REV>(x, x, alpha, v, base, false, si, u0,
+                                                              tile_full<V, SLOTS>(si, u0));
+                if constexpr (FUSED) part = wave_sum(fused_partial<IDT, ROP, RACC, SLOTS>(x, y));
+            }
+            if (!ws_wait(&s_done[slot], 5 * fill, a)) return false;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) s_data[slot][(w * SLOTS + s) * 64 + l] = x[s];
+            if (l == 0) {
+                s_wt[slot][w] = run;
+                s_red[slot][w] = part;
+                lds_add(&s_ready[slot], 1);
+            }
+            return true;
+        };
+        oka = issue(0, sa, xa, ya);
+        okb = issue(1, sb, xb, yb);
+        for (int64_t k = 0; k < K; k += 2) {
+            if (!stage(k, oka, sa, xa, ya)) return;
+            oka = issue(k + 2, sa, xa, ya);
+            if (k + 1 >= K) break;
+            if (!stage(k + 1, okb, sb, xb, yb)) return;
+            okb = issue(k + 3, sb, xb, yb);
+        }
+        return;
+    }
+    if (w < 8) {
+        // writers
+        const int ww = w - 4;
+        for (int64_t k = 0; k < K; ++k) {
+            const int slot = (int)(k % R);
+            const int fill = (int)(k / R) + 1;
+            if (!ws_wait(&s_ready[slot], 4 * fill, a)) return;
+            if (!ws_wait(&s_cseq[slot], fill, a)) return;
+            vec<IDT> x[SLOTS];
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) x[s] = s_data[slot][(ww * SLOTS + s) * 64 + l];
+            L woff = (L)0;
+            for (int i = 0; i < ww; ++i) woff += s_wt[slot][i];
+            const C cin = s_carry[slot];
+            const int64_t r = proc(k);
+            const int64_t t = phys(r);
+            SegInfo si;
+            const bool ok = tm.find(a, t, si);
+            __builtin_amdgcn_s_waitcnt(0xc07f);   // every LDS read of the slot is done
+            if (l == 0) lds_add(&s_done[slot], 1);
+            if (!ok) continue;   // malformed row (flagged)
+            const int64_t u0 = (t - si.first) * a.tile;
+            const bool full = tile_full<V, SLOTS>(si, u0);
+            L v[SLOTS][V];
+            L base[SLOTS];
+            (void)tile_values<IDT, OP, false, SLOTS, REV>(x, x, alpha, v, base, false, si, u0, full);
+            C excl = r == stop_of<REV>(a, si, T) ? (C)0 : cin;
+            if (a.flags & kFlagHasInit) excl = init_carry<C, IDT>(a) + excl;
+            tile_write<IDT, ODT, C64, SLOTS, REV>(v, base, excl, woff, si, u0, ww, l, full,
+                                                  (a.flags & DR_SCAN_EXCLUSIVE) != 0);
+        }
+        return;
+    }
+    if (w == 8) {
+        // publisher: tile totals (and the fused partials) in order
+        for (int64_t k = 0; k < K; ++k) {
+            const int slot = (int)(k % R);
+            const int fill = (int)(k / R) + 1;
+            if (!ws_wait(&s_ready[slot], 4 * fill, a)) return;
+            L tl = (L)0;
+            for (int i = 0; i < 4; ++i) tl += s_wt[slot][i];
+            double part = 0.0;
+            if (l == 0)
+                for (int i = 0; i < 4; ++i) part += s_red[slot][i];
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            if (l == 0) lds_add(&s_done[slot], 1);
+            const int64_t r = proc(k);
+            const int64_t t = phys(r);
+            SegInfo si;
+            const bool ok = tm.find(a, t, si);
+            const bool head = !ok || r == stop_of<REV>(a, si, T);
+            if (l == 0) ws_publish<C>(tws + r * TW, tag, head, ok ? (C)tl : (C)0);
+            if constexpr (FUSED) {
+                if (ok) {
+                    if (a.mode == DR_MODE_BATCH) combine_tile_batch<double>(a, tag, t, si, part);
+                    else combine_member<double>(a, tag, 0, 0, t, T, 0, part);
+                }
+            }
+        }
+        return;
+    }
+    // carry fetcher: lane j serves ring entry kn + j (j < R), one round trip
+    int64_t kn = 0;
+    int nap = 1;
+    Deadline dl(a.spin_ticks);
+    while (kn < K) {
+        const int64_t k = kn + l;
+        const bool mine = l < R && k < K;
+        const int slot = (int)(k % R);
+        const int fill = (int)(k / R) + 1;
+        bool okc = false;
+        C c = (C)0;
+        if (mine && lds_ld(&s_done[slot]) >= 5 * (fill - 1)) {
+            const int64_t r = proc(k);
+            if (r == 0) {
+                okc = true;
+            } else {
+                uint64_t bits = 0;
+                okc = tagged_load(tws + (r - 1) * TW + kInclWord, tag, bits);
+                c = from_bits<C>(bits);
+            }
+        }
+        const uint64_t okm = __ballot(okc);
+        const int m = (int)__builtin_ctzll(~okm);   // entries ready, in order
+        if (l < m) {
+            s_carry[slot] = c;
+            lds_st(&s_cseq[slot], fill);
+        }
+        kn += m;
+        if (m > 0) {
+            nap = 1;
+            dl = Deadline(a.spin_ticks);
+        } else {
+            if (dl.passed()) {
+                if (l == 0) flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
+                return;
+            }
+            for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(1);
+            nap = nap < 4 ? 2 * nap : 4;
+        }
+    }
+}
+
+template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
+hipError_t launch_scan_ws(const LaunchArgs& a, hipStream_t stream) {
+    const void* fn = (const void*)k_scan_ws<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, REV>;
+    static const int resident = resident_grid(fn, kWsThreads);
+    if (resident < 2) return hipErrorCooperativeLaunchTooLarge;
+    LaunchArgs arg = a;
+    void* args[] = {&arg};
+    return hipLaunchCooperativeKernel(fn, dim3((uint32_t)resident), dim3(kWsThreads), args, 0, stream);
+}
+
 template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV, int CMB>
 hipError_t launch_scan_dir(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
     if constexpr (CMB == kCmbSum) {
@@ -688,11 +1124,23 @@ hipError_t launch_scan_dir(const LaunchArgs& a, int64_t grid, hipStream_t stream
 
 template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, int CMB = kCmbSum>
 hipError_t launch_scan(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
-    // the prologue (epoch tag, zeroed counters) serves the single-pass form
+    constexpr bool WS = CMB == kCmbSum && ws_form<IDT, ODT, OP, FUSED, ITEMS>();
+    const bool ws = WS && (a.flags & kFlagSpecialized) != 0;
+    // the prologue (epoch tag, zeroed counters) serves the single-pass forms
     // and the fused reduction's combine
-    if (FUSED || (CMB == kCmbSum && (a.flags & kFlagTilePerBlock))) {
+    if (FUSED || ws || (CMB == kCmbSum && (a.flags & kFlagTilePerBlock))) {
         hipError_t e = launch_prologue(a, stream);
         if (e != hipSuccess) return e;
+    }
+    if constexpr (WS) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (ws && hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+            const hipError_t e = (a.flags & DR_SCAN_REVERSE)
+                                     ? launch_scan_ws<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, true>(a, stream)
+                                     : launch_scan_ws<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, false>(a, stream);
+            if (e == hipSuccess) return e;
+            (void)hipGetLastError();   // the grid cannot be held at once: the two passes instead
+        }
     }
     if (a.flags & DR_SCAN_REVERSE)
         return launch_scan_dir<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, true, CMB>(a, grid, stream);
@@ -722,12 +1170,14 @@ LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items) {
     DR_SCAN_ID(DR_I32, DR_I64, true, 32)
     DR_SCAN_ID(DR_I32, DR_I64, true, 64)
     DR_SCAN_OPS(DR_I32, DR_I32, true, 16)
+    DR_SCAN_ID(DR_I32, DR_I32, true, 32)
     DR_SCAN_ID(DR_I32, DR_I32, true, 64)
     DR_SCAN_OPS(DR_F32, DR_F32, true, 16)
     DR_SCAN_ID(DR_F32, DR_F32, true, 32)
     DR_SCAN_ID(DR_F32, DR_F32, true, 64)
     DR_SCAN_OPS(DR_F32, DR_F32, false, 16)
     DR_SCAN_OPS(DR_BF16, DR_F32, true, 16)
+    DR_SCAN_ID(DR_BF16, DR_F32, true, 32)
     DR_SCAN_ID(DR_BF16, DR_F32, true, 64)
     DR_SCAN_OPS(DR_F64, DR_F64, true, 16)
     DR_SCAN_ID(DR_F64, DR_F64, true, 32)

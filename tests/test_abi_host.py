@@ -199,6 +199,13 @@ def test_generic_operator_argument_errors():
     assert scan(v, B.DR_COMBINE_MIN, flags=B.DR_SCAN_CARRY_F32) == -2
     assert scan(v, B.DR_COMBINE_MAX, tuning=B.make_tuning(16, B.DR_TUNE_TILE_PER_BLOCK)) == -2
     assert scan(v, B.DR_COMBINE_MAX, tuning=B.make_tuning(64)) == -2
+    # the specialised-wave form: sums of the identity view at its own tile size
+    ws_tu = B.make_tuning(B.WS_ITEMS[B.DR_F32], B.DR_TUNE_SPECIALIZED)
+    assert scan(v, B.DR_COMBINE_MAX, tuning=ws_tu) == -2
+    assert scan(sq, B.DR_COMBINE_SUM, tuning=ws_tu) == -2                  # square view: not built
+    assert scan(v, B.DR_COMBINE_SUM, tuning=B.make_tuning(16, B.DR_TUNE_SPECIALIZED)) == -2
+    assert b"items per thread" in L.dr_last_error()
+    assert scan(v, B.DR_COMBINE_SUM, tuning=B.make_tuning(32, B.DR_TUNE_SPECIALIZED | B.DR_TUNE_TILE_PER_BLOCK)) == -1
     assert scan(v, B.DR_COMBINE_MAX, out=B.DR_I64) == -2                     # f32 -> i64 not a scan pair
     # the exclusive flag belongs to dr_scan, not dr_inclusive_scan
     assert _call_scan(t, v, flags=B.DR_SCAN_EXCLUSIVE) == -1

@@ -1,9 +1,11 @@
-"""Run-to-run reproducibility of the default forms. The reduce-then-scan
-carries are combined in a fixed order (tile records relative to their chunk,
-then one fixed-shape scan of the chunk records), and reductions combine tile
-partials in member order over a fixed tree, so repeated calls give the same
-bits for floating-point inputs, not just results within the error bound.
-The workspace is shared between the calls, as a caller's would be."""
+"""Run-to-run reproducibility of the default forms and of the single pass
+with specialised waves. The reduce-then-scan carries are combined in a fixed
+order (tile records relative to their chunk, then one fixed-shape scan of the
+chunk records); the specialised form's agent scans the published tile totals
+with a fixed shape; reductions combine tile partials in member order over a
+fixed tree. So repeated calls give the same bits for floating-point inputs,
+not just results within the error bound. The workspace is shared between the
+calls, as a caller's would be."""
 import numpy as np
 import pytest
 import torch
@@ -38,8 +40,12 @@ def _input(in_dt, n, seed):
 @pytest.mark.parametrize("reverse", [False, True])
 @pytest.mark.parametrize("in_dt,out_dt,flags", [(B.DR_F32, B.DR_F32, 0), (B.DR_F32, B.DR_F32, B.DR_SCAN_CARRY_F32),
                                                 (B.DR_BF16, B.DR_F32, 0), (B.DR_F64, B.DR_F64, 0)])
-def test_float_scans_repeat_bit_for_bit(mode, reverse, in_dt, out_dt, flags):
-    announce("scan repeat", mode, reverse, in_dt, flags)
+@pytest.mark.parametrize("form", ["default", "specialized"])
+def test_float_scans_repeat_bit_for_bit(mode, reverse, in_dt, out_dt, flags, form):
+    if form == "specialized" and flags & B.DR_SCAN_CARRY_F32:
+        pytest.skip("the specialised-wave form keeps binary64 carries")
+    tuning = B.make_tuning(B.WS_ITEMS[in_dt], B.DR_TUNE_SPECIALIZED) if form == "specialized" else None
+    announce("scan repeat", mode, reverse, in_dt, flags, form)
     x = _input(in_dt, sum(LENGTHS), 901)
     ins = place(x, LENGTHS, "separate")
     ws = B.Workspace(dev())
@@ -50,7 +56,7 @@ def test_float_scans_repeat_bit_for_bit(mode, reverse, in_dt, out_dt, flags):
             o.fill_(float(rep) + 0.5)          # stale contents differ between the calls
         tab = B.segments([ins], [outs], mode=mode)
         B.dr_inclusive_scan(tab, B.make_view("identity", in_dt), out_dt,
-                            flags | (B.DR_SCAN_REVERSE if reverse else 0), workspace=ws)
+                            flags | (B.DR_SCAN_REVERSE if reverse else 0), workspace=ws, tuning=tuning)
         got = _bits(outs)
         if first is None:
             first = got
@@ -80,8 +86,10 @@ def test_dot_repeats_bit_for_bit(mode, acc):
     assert ws.device_status() == 0
 
 
-def test_fused_scan_reduce_repeats_bit_for_bit():
-    announce("fused repeat")
+@pytest.mark.parametrize("form", ["default", "specialized"])
+def test_fused_scan_reduce_repeats_bit_for_bit(form):
+    announce("fused repeat", form)
+    tuning = B.make_tuning(B.WS_ITEMS_FUSED, B.DR_TUNE_SPECIALIZED) if form == "specialized" else None
     lengths = I.lengths_loguniform(3000, 1 << 18, 1 << 22, 904)
     n = sum(lengths)
     x, y = I.normal_f32(n, 905), I.normal_f32(n, 906)
@@ -93,7 +101,7 @@ def test_fused_scan_reduce_repeats_bit_for_bit():
         res = torch.full((len(lengths),), float(rep), dtype=torch.float64, device=dev())
         tab = B.segments(ins, [outs], mode="batch")
         B.dr_scan_reduce(tab, B.make_view("identity", B.DR_F32), B.make_view("mul", B.DR_F32),
-                         B.DR_ACC_COMPENSATED, 0.0, res, workspace=ws)
+                         B.DR_ACC_COMPENSATED, 0.0, res, workspace=ws, tuning=tuning)
         got = (_bits(outs), res.view(torch.int64).clone())
         if first is None:
             first = got

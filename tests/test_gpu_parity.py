@@ -189,13 +189,22 @@ SCAN_CASES = [(B.DR_I32, B.DR_I64), (B.DR_I32, B.DR_I32), (B.DR_F32, B.DR_F32), 
 # the single pass), the reduce-then-scan passes requested explicitly, and the
 # single-pass form (one workgroup per tile in block-index order, decoupled
 # look-back)
-SCAN_FORMS = ["default", "two_pass", "look_back"]
+SCAN_FORMS = ["default", "two_pass", "look_back", "specialized"]
 
 
-def _scan_tuning(form, items=16):
+def _scan_tuning(form, items=16, in_dt=B.DR_F32, fused=False):
     if form == "default":
         return None
+    if form == "specialized":
+        return B.make_tuning(_form_items(form, in_dt, fused), B.DR_TUNE_SPECIALIZED)
     return B.make_tuning(items, B.DR_TUNE_TILE_PER_BLOCK if form == "look_back" else 0)
+
+
+def _form_items(form, in_dt=B.DR_F32, fused=False):
+    """Items per thread of a scan form's tiles (the error bounds depend on it)."""
+    if form == "specialized":
+        return B.WS_ITEMS_FUSED if fused else B.WS_ITEMS[in_dt]
+    return 16
 
 
 @pytest.mark.parametrize("seg_name,lengths", SEGMENTATIONS)
@@ -206,6 +215,8 @@ def _scan_tuning(form, items=16):
 def test_inclusive_scan(seg_name, lengths, in_dt, out_dt, mode, reverse, form):
     op = B.DR_OP_IDENTITY
     layout, offs = LAYOUTS[(len(lengths) + int(reverse)) % len(LAYOUTS)]
+    if form == "specialized" and out_dt == B.DR_I64:
+        pytest.skip("int32 -> int64 scans keep the two passes")
     announce("scan", seg_name, in_dt, out_dt, mode, reverse, layout, form)
     n = sum(lengths)
     x = _values(in_dt, n, 21)
@@ -214,7 +225,7 @@ def test_inclusive_scan(seg_name, lengths, in_dt, out_dt, mode, reverse, form):
     outs = empty_like_segments(lengths, B.TORCH_DTYPE[out_dt], "separate")
     tab, _ = _table([x], lengths, layout, outs=[outs], mode=mode, offsets=(offs or [0])[:1])
     B.dr_inclusive_scan(tab, B.make_view(op, in_dt), out_dt, B.DR_SCAN_REVERSE if reverse else 0,
-                        tuning=_scan_tuning(form))
+                        tuning=_scan_tuning(form, in_dt=in_dt))
     got = gather(outs)
     omode = O.BATCH if mode == "batch" else O.CONCAT
     if in_dt == B.DR_I32:
@@ -228,7 +239,7 @@ def test_inclusive_scan(seg_name, lengths, in_dt, out_dt, mode, reverse, form):
     if in_dt == B.DR_F64:
         bound = 40 * U64 * absp + U64 * np.abs(ref)
     else:
-        bound = scan_fp32_bound(ref, absp, tiles=n // 4096 + len(lengths))
+        bound = scan_fp32_bound(ref, absp, items=_form_items(form, in_dt), tiles=n // 4096 + len(lengths))
     err = np.abs(got.astype(np.float64) - ref)
     assert np.all(err <= bound), (err.max(), int(np.argmax(err - bound)))
 
@@ -309,16 +320,17 @@ def test_scan_reduce_fused(mode, reverse, form):
     res = torch.zeros(nres, dtype=torch.float64, device=dev())
     B.dr_scan_reduce(tab, B.make_view("identity", B.DR_F32), B.make_view("mul", B.DR_F32),
                      B.DR_ACC_COMPENSATED, 0.0, res, B.DR_SCAN_REVERSE if reverse else 0,
-                     tuning=_scan_tuning(form))
+                     tuning=_scan_tuning(form, fused=True))
     omode = O.BATCH if mode == "batch" else O.CONCAT
     ref, absp = O.scan(I.split(x, lengths), None, O.F32, O.IDENTITY, mode=omode, reverse=reverse, want_abs=True)
     ref, absp = np.concatenate(ref), np.concatenate(absp)
+    items = _form_items(form, fused=True)
     err = np.abs(gather(outs).astype(np.float64) - ref)
-    assert np.all(err <= scan_fp32_bound(ref, absp, tiles=n // 4096 + len(lengths)))
+    assert np.all(err <= scan_fp32_bound(ref, absp, items=items, tiles=n // 4096 + len(lengths)))
     want, mag = O.reduce(I.split(x, lengths), I.split(y, lengths), O.F32, O.MUL, mode=omode)
     got = dev_to_np(res)
     for g, w, a in zip(got, want, mag):
-        assert abs(g - w) <= reduce_bound(a, "compensated", tiles=n // 4096 + len(lengths))
+        assert abs(g - w) <= reduce_bound(a, "compensated", items=items, tiles=n // 4096 + len(lengths))
 
 
 # --- adjoint broadcast multiply ----------------------------------------------------------
