@@ -174,9 +174,16 @@ class Table:
     keep: list = field(repr=False, default_factory=list)
 
     def c_table(self, host_check: bool = True) -> dr_table:
+        # the struct is rebuilt only when a field it mirrors has changed
         rows = self.dev_rows.data_ptr() if self.n_segments else None
+        key = (host_check, rows, self.n_segments, self.total_length, self.mode)
+        cached = self.__dict__.get("_c_cache")
+        if cached is not None and cached[0] == key:
+            return cached[1]
         host = ctypes.addressof(self.host_rows) if (host_check and self.n_segments) else None
-        return dr_table(rows, host, self.n_segments, self.total_length, self.mode, 0)
+        c = dr_table(rows, host, self.n_segments, self.total_length, self.mode, 0)
+        self.__dict__["_c_cache"] = (key, c)
+        return c
 
 
 def segments(inputs, outputs=None, mode: int | str = DR_MODE_CONCAT, device=None,
@@ -234,6 +241,7 @@ class Workspace:
         self.device = torch.device(device) if device is not None else torch.device("cuda")
         self.buf = None
         self.plan_key = None
+        self._sizes = {}   # (algo, rows, length, view dtype/op/arity, tuning) -> bytes
 
     @property
     def ptr(self) -> int:
@@ -254,11 +262,16 @@ class Workspace:
         self.plan_key = None
 
     def for_call(self, algo: int, table: Table, view: dr_view, tuning: dr_tuning | None) -> None:
-        size = ctypes.c_size_t(0)
         tptr = ctypes.byref(tuning) if tuning is not None else None
-        check(lib().dr_workspace_bytes(algo, table.n_segments, table.total_length, ctypes.byref(view),
-                                       tptr, ctypes.byref(size)))
-        self.ensure(size.value)
+        tkey = (tuning.block_threads, tuning.items_per_thread, tuning.flags, tuning.reserved) if tuning else None
+        skey = (algo, table.n_segments, table.total_length, view.in_dtype, view.op, view.arity, tkey)
+        nbytes = self._sizes.get(skey)
+        if nbytes is None:
+            size = ctypes.c_size_t(0)
+            check(lib().dr_workspace_bytes(algo, table.n_segments, table.total_length, ctypes.byref(view),
+                                           tptr, ctypes.byref(size)))
+            nbytes = self._sizes[skey] = size.value
+        self.ensure(nbytes)
         if table.n_segments > DR_SMALL_TABLE:
             # a plan is built for one tile size: the algorithm and the tuning
             # fix it (the defaults differ between algorithms and dtypes)
