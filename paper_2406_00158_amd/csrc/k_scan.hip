@@ -677,6 +677,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
 //   wave 8     publishes each tile's total (and, fused, its dot partial and
 //              the combine) as soon as the loaders have it;
 //   wave 9     fetches the carries of the next ring slots in one round trip.
+// The agent's two waves past the scanning ones store the prefixes it
+// computes (handed over in LDS), so that its polls never wait behind its
+// own stores in the in-order memory counter.
 // The agent scans the published tile totals in windows of kWsWindow tiles
 // with a fixed shape (a serial pass over each thread's tiles, a wave scan,
 // the waves in order, the window's carry in), so every carry is the same
@@ -737,6 +740,7 @@ __device__ void ws_agent(const LaunchArgs& a, uint32_t tag, int64_t T) {
     __shared__ int s_wh[kWsAgentWaves];
     __shared__ C s_last;
     __shared__ int s_to;
+    __shared__ C s_I[kWsWindow];   // prefixes handed to the storing waves
     constexpr int PT = kWsPerThread;
     uint64_t* tws = (uint64_t*)(a.ws + a.lay.off_tile);
     const int64_t TW = a.lay.tile_words;
@@ -833,12 +837,17 @@ __device__ void ws_agent(const LaunchArgs& a, uint32_t tag, int64_t T) {
                 for (int j = 0; j < PT; ++j) {
                     const int idx = PT * tid + j;
                     const C I = loch[j] ? loc[j] : c + loc[j];
-                    if (idx >= pub && idx < (int)z) tagged_store(tws + (base + idx) * TW + kInclWord, tag, to_bits(I));
+                    if (idx >= pub && idx < (int)z) s_I[idx] = I;
                     if (idx == n - 1 && (int)z == n) s_last = I;
                 }
             }
             if (tid == 0) s_to = ((int)z < n && dl.passed()) ? 1 : 0;
             __syncthreads();
+            // the waves past the scanning ones store the new prefixes: the
+            // scanning waves only load, so no poll waits behind a store
+            for (int idx = pub + tid - 64 * kWsAgentWaves; w >= kWsAgentWaves && idx < (int)z;
+                 idx += 64 * (kWsWaves - kWsAgentWaves))
+                tagged_store(tws + (base + idx) * TW + kInclWord, tag, to_bits(s_I[idx]));
             const bool progress = (int)z > pub;
             pub = (int)z;
             if ((int)z == n) {
