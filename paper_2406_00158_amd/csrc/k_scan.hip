@@ -891,7 +891,7 @@ int ws_items_for(int in_dt, bool fused) {
     return in_dt == DR_F64 ? 16 : 32;
 }
 
-template <int IDT, int ITEMS, bool FUSED>
+template <int IDT, int ITEMS>
 constexpr int ws_ring() {
     constexpr int bytes = kBlock * ITEMS * esize<IDT>();
     constexpr int r = kWsLdsBytes / bytes;
@@ -902,7 +902,7 @@ template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int
 __global__ __launch_bounds__(kWsThreads) void k_scan_ws(LaunchArgs a) {
     constexpr int V = vwidth<IDT>();
     constexpr int SLOTS = ITEMS / V;
-    constexpr int R = ws_ring<IDT, ITEMS, FUSED>();
+    constexpr int R = ws_ring<IDT, ITEMS>();
     static_assert(R >= 2, "the ring needs two slots");
     using L = local_t<IDT>;
     using C = carry_t<IDT, C64>;
