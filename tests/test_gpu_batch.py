@@ -112,3 +112,49 @@ def test_autotuner_picks_and_caches(tmp_path, monkeypatch):
     _run(tab, res, ws, tu)
     want, mag = O.reduce(I.split(xs, lengths), I.split(ys, lengths), O.F32, O.MUL, mode=O.BATCH)
     assert np.all(np.abs(dev_to_np(res) - want) <= reduce_bound(mag, "compensated", items=64, tiles=64))
+
+
+def test_specialized_scan_under_graph_capture_runs_two_passes():
+    """A cooperative launch cannot be captured: a scan asking for the
+    specialised-wave form inside a capture runs the two passes instead. Every
+    replay is checked against the oracle, with eager work between replays,
+    and the replays repeat each other bit for bit."""
+    announce("specialised form under capture")
+    lengths = [200_000, 0, 123_457, 77]
+    n = sum(lengths)
+    xs = I.normal_f32(n, 31)
+    x = torch.from_numpy(xs).to(dev())
+    s = torch.empty_like(x)
+    tab = B.segments([_carve(x, lengths)], [_carve(s, lengths)])
+    view = B.make_view("identity", B.DR_F32)
+    tu = B.make_tuning(B.WS_ITEMS[B.DR_F32], B.DR_TUNE_SPECIALIZED)
+    ws = B.Workspace(dev())
+    ref, absp = O.scan(I.split(xs, lengths), None, O.F32, O.IDENTITY, want_abs=True)
+    ref, absp = np.concatenate(ref), np.concatenate(absp)
+    bound = scan_fp32_bound(ref, absp, items=B.WS_ITEMS[B.DR_F32], tiles=n // 8192 + len(lengths))
+    B.dr_inclusive_scan(tab, view, B.DR_F32, workspace=ws, tuning=tu)      # eager: the specialised form
+    torch.cuda.synchronize()
+    assert np.all(np.abs(dev_to_np(s).astype(np.float64) - ref) <= bound)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.dr_inclusive_scan(tab, view, B.DR_F32, workspace=ws, tuning=tu)
+    torch.cuda.current_stream().wait_stream(side)
+    with torch.cuda.graph(g):
+        B.dr_inclusive_scan(tab, view, B.DR_F32, workspace=ws, tuning=tu)
+    first = None
+    for rep in range(3):
+        s.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = dev_to_np(s)
+        assert np.all(np.abs(got.astype(np.float64) - ref) <= bound), f"replay {rep}"
+        if first is None:
+            first = got.copy()
+        else:
+            assert np.array_equal(got.view(np.uint32), first.view(np.uint32)), f"replay {rep} differs"
+        B.dr_inclusive_scan(tab, view, B.DR_F32, workspace=ws, tuning=tu)   # eager work between replays
+        torch.cuda.synchronize()
+    assert ws.device_status() == 0
