@@ -423,10 +423,10 @@ static bool prefer_single_pass(const dr_table* t, int in_dt, const dr_tuning* tu
 
 // The single pass with specialised waves, on request (DR_TUNE_SPECIALIZED,
 // at the form's own tile size). It is not the default: at 2^28 binary32
-// elements it measured 524 us against 507 us for the two passes, and the
-// fused form (16 items per thread, twice the tiles for its carry chain)
-// 1140 us against 723 us. On success `use` is the tuning to prepare with
-// and `on` says whether the form runs.
+// elements it measured level with the two passes (513-517 us against
+// 511 us), and the fused form (16 items per thread, twice the tiles for its
+// carry chain) 1108 us against 725 us. On success `use` is the tuning to
+// prepare with and `on` says whether the form runs.
 static dr_status specialized_tuning(int in_dt, int out_dt, int op, bool fused, bool c64,
                                     int acc, const dr_tuning* tu, dr_tuning& tmp, const dr_tuning*& use,
                                     bool& on) {

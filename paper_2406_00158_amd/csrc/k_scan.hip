@@ -783,12 +783,10 @@ __device__ void ws_agent(const LaunchArgs& a, uint32_t tag, int64_t T) {
                 for (int j = PT - 1; j >= 0; --j)
                     if (PT * tid + j < n && !have[j]) fm = (uint32_t)(PT * tid + j);
             }
-            uint32_t wm = fm;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                const uint32_t o = (uint32_t)__shfl_xor((int)wm, d, 64);
-                wm = wm < o ? wm : o;
-            }
+            // the first missing index of the wave is that of its first lane
+            // with one (lanes hold increasing indices)
+            const uint64_t missing = __ballot(fm != 0xffffffffu);
+            const uint32_t wm = missing ? (uint32_t)readlane((int)fm, __builtin_ctzll(missing)) : 0xffffffffu;
             if (l == 0) s_zmin[w] = wm;
             // fixed-shape segmented scan of the window; unpublished entries
             // are the identity and only ever feed later ones
@@ -805,17 +803,20 @@ __device__ void ws_agent(const LaunchArgs& a, uint32_t tag, int64_t T) {
                 loc[j] = run;
                 loch[j] = rh;
             }
+            // segmented inclusive scan over the wave with DPP row shifts and
+            // broadcasts (lanes without a source receive the identity (0, 0))
             C sv = run;
             int sh = rh ? 1 : 0;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const C pv = __shfl_up(sv, d, 64);
-                const int ph = __shfl_up(sh, d, 64);
-                if (l >= d) {
-                    if (!sh) sv = pv + sv;
-                    sh = sh | ph;
-                }
-            }
+            auto seg_step = [&](C pv, int ph) {
+                if (!sh) sv = pv + sv;
+                sh = sh | ph;
+            };
+            seg_step(dpp_move<DPP_ROW_SHR1, 0xf>(sv), dpp_move<DPP_ROW_SHR1, 0xf>(sh));
+            seg_step(dpp_move<DPP_ROW_SHR2, 0xf>(sv), dpp_move<DPP_ROW_SHR2, 0xf>(sh));
+            seg_step(dpp_move<DPP_ROW_SHR4, 0xf>(sv), dpp_move<DPP_ROW_SHR4, 0xf>(sh));
+            seg_step(dpp_move<DPP_ROW_SHR8, 0xf>(sv), dpp_move<DPP_ROW_SHR8, 0xf>(sh));
+            seg_step(dpp_move<DPP_ROW_BCAST15, 0xa>(sv), dpp_move<DPP_ROW_BCAST15, 0xa>(sh));
+            seg_step(dpp_move<DPP_ROW_BCAST31, 0xc>(sv), dpp_move<DPP_ROW_BCAST31, 0xc>(sh));
             if (w < kWsAgentWaves && l == 63) {
                 s_wt[w] = sv;
                 s_wh[w] = sh;
