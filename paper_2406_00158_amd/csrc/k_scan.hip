@@ -1054,35 +1054,47 @@ __global__ __launch_bounds__(kWsThreads) void k_scan_ws(LaunchArgs a) {
         }
         return;
     }
-    // carry fetcher: lane j serves ring entry kn + j (j < R), one round trip
+    // carry fetcher: lane j looks after entry kn + j (j < 2R). It fetches
+    // the entry's carry as soon as the agent has published it (one round
+    // trip for every lane) and keeps it in a register until the entry's ring
+    // slot is free, so a freed slot gets its carry at once.
+    constexpr int LA = 2 * R;
     int64_t kn = 0;
+    bool got = false;
+    C c = (C)0;
     int nap = 1;
     Deadline dl(a.spin_ticks);
     while (kn < K) {
         const int64_t k = kn + l;
-        const bool mine = l < R && k < K;
-        const int slot = (int)(k % R);
-        const int fill = (int)(k / R) + 1;
-        bool okc = false;
-        C c = (C)0;
-        if (mine && lds_ld(&s_done[slot]) >= 5 * (fill - 1)) {
+        const bool mine = l < LA && k < K;
+        if (mine && !got) {
             const int64_t r = proc(k);
             if (r == 0) {
-                okc = true;
+                got = true;
             } else {
                 uint64_t bits = 0;
-                okc = tagged_load(tws + (r - 1) * TW + kInclWord, tag, bits);
-                c = from_bits<C>(bits);
+                if (tagged_load(tws + (r - 1) * TW + kInclWord, tag, bits)) {
+                    got = true;
+                    c = from_bits<C>(bits);
+                }
             }
         }
-        const uint64_t okm = __ballot(okc);
-        const int m = (int)__builtin_ctzll(~okm);   // entries ready, in order
+        const int slot = (int)(k % R);
+        const int fill = (int)(k / R) + 1;
+        const bool ready = mine && got && lds_ld(&s_done[slot]) >= 5 * (fill - 1);
+        const uint64_t okm = __ballot(ready);
+        const int m = (int)__builtin_ctzll(~okm);   // entries delivered, in order
         if (l < m) {
             s_carry[slot] = c;
             lds_st(&s_cseq[slot], fill);
         }
-        kn += m;
         if (m > 0) {
+            // lane j takes over the state of lane j + m
+            const int g2 = __shfl_down(got ? 1 : 0, m, 64);
+            const C c2 = __shfl_down(c, m, 64);
+            got = l + m < LA && g2 != 0;
+            c = c2;
+            kn += m;
             nap = 1;
             dl = Deadline(a.spin_ticks);
         } else {
