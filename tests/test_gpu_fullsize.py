@@ -109,14 +109,16 @@ def test_int_scan_2_30(out_dt):
     assert np.array_equal(got, want)
 
 
-def test_fp32_scan_2_28_f64_carry():
+@pytest.mark.parametrize("form", ["default", "specialized"])
+def test_fp32_scan_2_28_f64_carry(form):
     t = _workload("scan_fp")
     L = t["lengths"]
-    announce("fp scan 2^28")
+    announce("fp scan 2^28", form)
     x = _to_dev(t["x"])
     out = torch.empty_like(x)
+    tuning = B.make_tuning(B.WS_ITEMS[B.DR_F32], B.DR_TUNE_SPECIALIZED) if form == "specialized" else None
     B.dr_inclusive_scan(B.segments([_pieces(x, L)], [_pieces(out, L)]), B.make_view("identity", B.DR_F32),
-                        B.DR_F32)
+                        B.DR_F32, tuning=tuning)
     got = dev_to_np(out).astype(np.float64)
     ref, absp = O.scan(I.split(t["x"], L), None, O.F32, O.IDENTITY, want_abs=True)
     ref, absp = np.concatenate(ref), np.concatenate(absp)
@@ -125,7 +127,8 @@ def test_fp32_scan_2_28_f64_carry():
     exact = np.mean(got.astype(np.float32) == ref.astype(np.float32))
     print(f"fp scan: max abs err {err.max():.3e}, max err/A_i {scaled.max():.3e} (u32 = {U32:.3e}), "
           f"fraction equal to fl32(ref) {exact:.6f}")
-    assert np.all(err <= scan_fp32_bound(ref, absp, tiles=(1 << 28) // 4096 + 16))
+    items = B.WS_ITEMS[B.DR_F32] if form == "specialized" else 16
+    assert np.all(err <= scan_fp32_bound(ref, absp, items=items, tiles=(1 << 28) // 4096 + 16))
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
