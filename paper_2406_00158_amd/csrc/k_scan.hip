@@ -256,16 +256,24 @@ __device__ __forceinline__ local_t<IDT> tile_values(const vec<IDT, V> (&x)[SLOTS
     return run;
 }
 
-// Outputs of a tile: carry + offset of the wave + prefix inside the wave.
-// `exc`: exclusive scan (each output combines the elements strictly before
-// it in processing order).
-template <int IDT, int ODT, bool C64, int SLOTS, bool REV, int CMB = kCmbSum, int V = vwidth<IDT>()>
-__device__ __forceinline__ void tile_write(const local_t<IDT> (&v)[SLOTS][V],
-                                           const local_t<IDT> (&base)[SLOTS], carry_t<IDT, C64> excl,
-                                           local_t<IDT> woff, const SegInfo& si, int64_t u0, int w, int l,
-                                           bool full, bool exc = false, bool mn = false) {
+// One form of tile_write below. FULL: the tile lies wholly inside its segment with aligned rows, so every
+// slot is one unchecked vector store at a fixed stride from the lane's first
+// vector; otherwise each slot is checked on its own.
+template <int IDT, int ODT, bool C64, int SLOTS, bool REV, int CMB, int V, bool FULL>
+__device__ __forceinline__ void tile_write_part(const local_t<IDT> (&v)[SLOTS][V],
+                                                const local_t<IDT> (&base)[SLOTS], carry_t<IDT, C64> excl,
+                                                local_t<IDT> woff, const SegInfo& si, int64_t u0, int w, int l,
+                                                bool exc, bool mn) {
     using L = local_t<IDT>;
     using O = typename elem<ODT>::T;
+    constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+    constexpr int64_t step = (REV ? -64 : 64) * (int64_t)(V * sizeof(O));
+    char* tb = nullptr;
+    if constexpr (FULL) {
+        const int64_t p0 = (int64_t)(w * SLOTS) * 64 + l;
+        const int64_t q0 = REV ? NV - 1 - p0 : p0;
+        tb = (char*)si.out0 + (u0 - si.shift + q0 * V) * (int64_t)sizeof(O);
+    }
     const L id = cmb_id<CMB, L>(mn);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -281,8 +289,23 @@ __device__ __forceinline__ void tile_write(const local_t<IDT> (&v)[SLOTS][V],
         }
         (void)before;
         mirror_if(o, REV);
-        store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, REV, full, o);
+        if constexpr (FULL) store_run<O, V>(tb + s * step, 0, o);
+        else store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, REV, false, o);
     }
+}
+
+// Outputs of a tile: carry + offset of the wave + prefix inside the wave.
+// `exc`: exclusive scan (each output combines the elements strictly before
+// it in processing order). `full` (uniform) picks the unchecked form.
+template <int IDT, int ODT, bool C64, int SLOTS, bool REV, int CMB = kCmbSum, int V = vwidth<IDT>()>
+__device__ __forceinline__ void tile_write(const local_t<IDT> (&v)[SLOTS][V],
+                                           const local_t<IDT> (&base)[SLOTS], carry_t<IDT, C64> excl,
+                                           local_t<IDT> woff, const SegInfo& si, int64_t u0, int w, int l,
+                                           bool full, bool exc = false, bool mn = false) {
+    if (full)
+        tile_write_part<IDT, ODT, C64, SLOTS, REV, CMB, V, true>(v, base, excl, woff, si, u0, w, l, exc, mn);
+    else
+        tile_write_part<IDT, ODT, C64, SLOTS, REV, CMB, V, false>(v, base, excl, woff, si, u0, w, l, exc, mn);
 }
 
 // The caller's initial value in the carry type (scans with kFlagHasInit).
