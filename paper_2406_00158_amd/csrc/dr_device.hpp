@@ -640,21 +640,30 @@ __device__ __forceinline__ bool tile_full(const SegInfo& si, int64_t u0) {
     return si.vec_ok && j0 >= 0 && j0 + TILE <= si.n;
 }
 
+// The slots of a full tile (tile_full): whole vectors, no checks.
 template <int DT, int SLOTS, int V = vwidth<DT>()>
-__device__ __forceinline__ void load_slots(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
-                                           int64_t u0, int w, int l, bool rev) {
+__device__ __forceinline__ void load_slots_full(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
+                                                int64_t u0, int w, int l, bool rev) {
     using R = typename vbits<V * esize<DT>()>::T;
     constexpr int64_t NV = (int64_t)kBlock * SLOTS;
     const int64_t p0 = (int64_t)(w * SLOTS) * 64 + l;
-    if (tile_full<V, SLOTS>(si, u0)) {
-        const int64_t q0 = rev ? (NV - 1 - p0) : p0;
-        const char* b = (const char*)base + (u0 - si.shift + q0 * V) * esize<DT>();
-        const int64_t step = rev ? -64 * (int64_t)sizeof(R) : 64 * (int64_t)sizeof(R);
+    const int64_t q0 = rev ? (NV - 1 - p0) : p0;
+    const char* b = (const char*)base + (u0 - si.shift + q0 * V) * esize<DT>();
+    const int64_t step = rev ? -64 * (int64_t)sizeof(R) : 64 * (int64_t)sizeof(R);
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            R wv = __builtin_nontemporal_load((const R*)(b + s * step));
-            __builtin_memcpy(&x[s], &wv, sizeof(R));
-        }
+    for (int s = 0; s < SLOTS; ++s) {
+        R wv = __builtin_nontemporal_load((const R*)(b + s * step));
+        __builtin_memcpy(&x[s], &wv, sizeof(R));
+    }
+}
+
+template <int DT, int SLOTS, int V = vwidth<DT>()>
+__device__ __forceinline__ void load_slots(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
+                                           int64_t u0, int w, int l, bool rev) {
+    constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+    const int64_t p0 = (int64_t)(w * SLOTS) * 64 + l;
+    if (tile_full<V, SLOTS>(si, u0)) {
+        load_slots_full<DT, SLOTS, V>(x, base, si, u0, w, l, rev);
         return;
     }
 #pragma unroll
@@ -674,6 +683,19 @@ __device__ __forceinline__ void load_slots(vec<DT, V> (&x)[SLOTS], const void* b
             }
         }
     }
+}
+
+// load_slots with the tile's fullness known at compile time. A kernel that
+// loads several inputs calls this for each inside one branch on tile_full,
+// so the loads of a full tile are all issued before the first wait (with a
+// branch inside each call, the compiler joins the unchecked loads of one
+// input with the checked ones before the next input's, and that join waits
+// for every load in flight: the vector memory counter is in order).
+template <bool FULL, int DT, int SLOTS, int V = vwidth<DT>()>
+__device__ __forceinline__ void load_slots_k(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
+                                             int64_t u0, int w, int l, bool rev) {
+    if constexpr (FULL) load_slots_full<DT, SLOTS, V>(x, base, si, u0, w, l, rev);
+    else load_slots<DT, SLOTS, V>(x, base, si, u0, w, l, rev);
 }
 
 // Whether element e (memory order) of slot s of lane l of wave w lies
@@ -705,6 +727,22 @@ __device__ __forceinline__ void store_slot(void* base, const SegInfo& si, int64_
             const int64_t jj = j + e;
             if (jj >= 0 && jj < si.n) ((OT*)base)[jj] = o[e];
         }
+    }
+}
+
+// store_slot with the tile's fullness known at compile time: a full tile
+// (whole in its segment, rows aligned) stores each slot as one unchecked
+// vector, so the kernel branches once per tile rather than once per slot.
+template <bool FULL, class OT, int V, int SLOTS>
+__device__ __forceinline__ void store_slot_k(void* base, const SegInfo& si, int64_t u0, int w, int l, int s,
+                                             bool rev, const OT (&o)[V]) {
+    if constexpr (FULL) {
+        constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+        const int64_t p = (int64_t)(w * SLOTS + s) * 64 + l;
+        const int64_t q = rev ? (NV - 1 - p) : p;
+        store_run<OT, V>(base, u0 + q * V - si.shift, o);
+    } else {
+        store_slot<OT, V, SLOTS>(base, si, u0, w, l, s, rev, false, o);
     }
 }
 

@@ -94,19 +94,24 @@ __global__ __launch_bounds__(kBlock) void k_for_each(LaunchArgs a) {
     const auto alpha = alpha_of<IDT, ODT>(a.alpha);
 
     const bool full = tile_full<V, SLOTS>(si, u0);
-    vec<IDT> x[SLOTS], y[SLOTS];
-    load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, false);
-    if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, false);
+    auto body = [&](auto full_c) {
+        constexpr bool FULL = decltype(full_c)::value;
+        vec<IDT> x[SLOTS], y[SLOTS];
+        load_slots_k<FULL, IDT, SLOTS>(x, si.in0, si, u0, w, l, false);
+        if constexpr (ZIP) load_slots_k<FULL, IDT, SLOTS>(y, si.in1, si, u0, w, l, false);
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        O o[V];
+        for (int s = 0; s < SLOTS; ++s) {
+            O o[V];
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            typename elem<IDT>::T yv = ZIP ? y[s].e[e] : zero_elem<IDT>();
-            o[e] = Op::apply(x[s].e[e], yv, alpha);
+            for (int e = 0; e < V; ++e) {
+                typename elem<IDT>::T yv = ZIP ? y[s].e[e] : zero_elem<IDT>();
+                o[e] = Op::apply(x[s].e[e], yv, alpha);
+            }
+            store_slot_k<FULL, O, V, SLOTS>(si.out0, si, u0, w, l, s, false, o);
         }
-        store_slot<O, V, SLOTS>(si.out0, si, u0, w, l, s, false, full, o);
-    }
+    };
+    if (full) body(std::true_type{});
+    else body(std::false_type{});
 }
 
 // d op / d x_which, evaluated in binary64 (exact for F32/BF16 inputs).
@@ -137,24 +142,29 @@ __global__ __launch_bounds__(kBlock) void k_broadcast_mul(LaunchArgs a) {
     const double g = a.g[a.mode == DR_MODE_BATCH ? si.k : 0];
     const bool full = tile_full<V, SLOTS>(si, u0);
 
-    vec<IDT> x[SLOTS], y[SLOTS];
-    if constexpr (OP != DR_OP_IDENTITY) load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, false);
-    if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, false);
+    auto body = [&](auto full_c) {
+        constexpr bool FULL = decltype(full_c)::value;
+        vec<IDT> x[SLOTS], y[SLOTS];
+        if constexpr (OP != DR_OP_IDENTITY) load_slots_k<FULL, IDT, SLOTS>(x, si.in0, si, u0, w, l, false);
+        if constexpr (ZIP) load_slots_k<FULL, IDT, SLOTS>(y, si.in1, si, u0, w, l, false);
 #pragma unroll
-    for (int which = 0; which < NOUT; ++which) {
-        void* out = which == 0 ? si.out0 : si.out1;
+        for (int which = 0; which < NOUT; ++which) {
+            void* out = which == 0 ? si.out0 : si.out1;
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            O o[V];
+            for (int s = 0; s < SLOTS; ++s) {
+                O o[V];
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                typename elem<IDT>::T xv = OP != DR_OP_IDENTITY ? x[s].e[e] : zero_elem<IDT>();
-                typename elem<IDT>::T yv = ZIP ? y[s].e[e] : zero_elem<IDT>();
-                o[e] = (O)(g * dview<IDT, OP>(xv, yv, which, a.alpha));
+                for (int e = 0; e < V; ++e) {
+                    typename elem<IDT>::T xv = OP != DR_OP_IDENTITY ? x[s].e[e] : zero_elem<IDT>();
+                    typename elem<IDT>::T yv = ZIP ? y[s].e[e] : zero_elem<IDT>();
+                    o[e] = (O)(g * dview<IDT, OP>(xv, yv, which, a.alpha));
+                }
+                store_slot_k<FULL, O, V, SLOTS>(out, si, u0, w, l, s, false, o);
             }
-            store_slot<O, V, SLOTS>(out, si, u0, w, l, s, false, full, o);
         }
-    }
+    };
+    if (full) body(std::true_type{});
+    else body(std::false_type{});
 }
 
 // Standard normal distribution function by Abramowitz & Stegun 26.2.17
@@ -198,30 +208,35 @@ __global__ __launch_bounds__(kBlock) void k_black_scholes(LaunchArgs a) {
     const int w = threadIdx.x >> 6, l = lane_id();
     const int64_t u0 = (t - si.first) * a.tile;
     const bool full = tile_full<V, SLOTS>(si, u0);
-    vec<DR_F32> S[SLOTS], K[SLOTS], T[SLOTS], sg[SLOTS];
-    load_slots<DR_F32, SLOTS>(S, si.in0, si, u0, w, l, false);
-    load_slots<DR_F32, SLOTS>(K, si.in1, si, u0, w, l, false);
-    load_slots<DR_F32, SLOTS>(T, si.in2, si, u0, w, l, false);
-    load_slots<DR_F32, SLOTS>(sg, si.in3, si, u0, w, l, false);
     const float r = (float)a.alpha;
     const float ln2 = 0.6931471805599453f, log2e = 1.4426950408889634f;
+    auto body = [&](auto full_c) {
+        constexpr bool FULL = decltype(full_c)::value;
+        vec<DR_F32> S[SLOTS], K[SLOTS], T[SLOTS], sg[SLOTS];
+        load_slots_k<FULL, DR_F32, SLOTS>(S, si.in0, si, u0, w, l, false);
+        load_slots_k<FULL, DR_F32, SLOTS>(K, si.in1, si, u0, w, l, false);
+        load_slots_k<FULL, DR_F32, SLOTS>(T, si.in2, si, u0, w, l, false);
+        load_slots_k<FULL, DR_F32, SLOTS>(sg, si.in3, si, u0, w, l, false);
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        float c[V], p[V];
+        for (int s = 0; s < SLOTS; ++s) {
+            float c[V], p[V];
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const float s0 = S[s].e[e], k0 = K[s].e[e], t0 = T[s].e[e], v0 = sg[s].e[e];
-            const float vst = v0 * __builtin_amdgcn_sqrtf(t0);
-            const float lsk = __builtin_amdgcn_logf(s0 * __builtin_amdgcn_rcpf(k0)) * ln2;   // ln(S/K)
-            const float d1 = (lsk + (r + 0.5f * v0 * v0) * t0) * __builtin_amdgcn_rcpf(vst);
-            const float d2 = d1 - vst;
-            const float kd = k0 * __builtin_amdgcn_exp2f(-r * t0 * log2e);                   // K exp(-rT)
-            c[e] = s0 * norm_cdf(d1) - kd * norm_cdf(d2);
-            p[e] = (c[e] - s0) + kd;
+            for (int e = 0; e < V; ++e) {
+                const float s0 = S[s].e[e], k0 = K[s].e[e], t0 = T[s].e[e], v0 = sg[s].e[e];
+                const float vst = v0 * __builtin_amdgcn_sqrtf(t0);
+                const float lsk = __builtin_amdgcn_logf(s0 * __builtin_amdgcn_rcpf(k0)) * ln2;   // ln(S/K)
+                const float d1 = (lsk + (r + 0.5f * v0 * v0) * t0) * __builtin_amdgcn_rcpf(vst);
+                const float d2 = d1 - vst;
+                const float kd = k0 * __builtin_amdgcn_exp2f(-r * t0 * log2e);                   // K exp(-rT)
+                c[e] = s0 * norm_cdf(d1) - kd * norm_cdf(d2);
+                p[e] = (c[e] - s0) + kd;
+            }
+            store_slot_k<FULL, float, V, SLOTS>(si.out0, si, u0, w, l, s, false, c);
+            store_slot_k<FULL, float, V, SLOTS>(si.out1, si, u0, w, l, s, false, p);
         }
-        store_slot<float, V, SLOTS>(si.out0, si, u0, w, l, s, false, full, c);
-        store_slot<float, V, SLOTS>(si.out1, si, u0, w, l, s, false, full, p);
-    }
+    };
+    if (full) body(std::true_type{});
+    else body(std::false_type{});
 }
 
 template <int ITEMS>
