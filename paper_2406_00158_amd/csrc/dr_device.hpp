@@ -657,15 +657,13 @@ __device__ __forceinline__ void load_slots_full(vec<DT, V> (&x)[SLOTS], const vo
     }
 }
 
+// The slots of any tile, each element checked against the segment (the
+// elements outside it read as 0).
 template <int DT, int SLOTS, int V = vwidth<DT>()>
-__device__ __forceinline__ void load_slots(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
-                                           int64_t u0, int w, int l, bool rev) {
+__device__ __forceinline__ void load_slots_checked(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
+                                                   int64_t u0, int w, int l, bool rev) {
     constexpr int64_t NV = (int64_t)kBlock * SLOTS;
     const int64_t p0 = (int64_t)(w * SLOTS) * 64 + l;
-    if (tile_full<V, SLOTS>(si, u0)) {
-        load_slots_full<DT, SLOTS, V>(x, base, si, u0, w, l, rev);
-        return;
-    }
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int64_t p = p0 + (int64_t)s * 64;
@@ -682,6 +680,28 @@ __device__ __forceinline__ void load_slots(vec<DT, V> (&x)[SLOTS], const void* b
                 x[s].e[e] = v;
             }
         }
+    }
+}
+
+template <int DT, int SLOTS, int V = vwidth<DT>()>
+__device__ __forceinline__ void load_slots(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
+                                           int64_t u0, int w, int l, bool rev) {
+    if (tile_full<V, SLOTS>(si, u0)) load_slots_full<DT, SLOTS, V>(x, base, si, u0, w, l, rev);
+    else load_slots_checked<DT, SLOTS, V>(x, base, si, u0, w, l, rev);
+}
+
+// The two inputs of a zipped view (y only when ZIP) under one branch on
+// tile_full, so that a full tile issues both inputs' loads before any wait
+// (see load_slots_k).
+template <bool ZIP, int DT, int SLOTS, int V = vwidth<DT>()>
+__device__ __forceinline__ void load_pair(vec<DT, V> (&x)[SLOTS], vec<DT, V> (&y)[SLOTS], const SegInfo& si,
+                                          int64_t u0, int w, int l, bool rev) {
+    if (tile_full<V, SLOTS>(si, u0)) {
+        load_slots_full<DT, SLOTS, V>(x, si.in0, si, u0, w, l, rev);
+        if constexpr (ZIP) load_slots_full<DT, SLOTS, V>(y, si.in1, si, u0, w, l, rev);
+    } else {
+        load_slots_checked<DT, SLOTS, V>(x, si.in0, si, u0, w, l, rev);
+        if constexpr (ZIP) load_slots_checked<DT, SLOTS, V>(y, si.in1, si, u0, w, l, rev);
     }
 }
 

@@ -653,8 +653,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
     const int64_t u0 = (t - si.first) * a.tile;
     const bool full = tile_full<V, SLOTS>(si, u0);
     vec<IDT, V> x[SLOTS], y[SLOTS];
-    load_slots<IDT, SLOTS, V>(x, si.in0, si, u0, w, l, REV);
-    if constexpr (ZIP) load_slots<IDT, SLOTS, V>(y, si.in1, si, u0, w, l, REV);
+    load_pair<ZIP, IDT, SLOTS, V>(x, y, si, u0, w, l, REV);
     double rpart_thread = 0.0;
     if constexpr (FUSED) rpart_thread = fused_partial<IDT, ROP, RACC, SLOTS>(x, y);
     const bool mn = (a.flags & kFlagMin) != 0;
