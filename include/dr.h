@@ -26,17 +26,20 @@
  *  - Ownership: the caller owns every buffer (inputs, outputs, the device
  *    segment table, the workspace, results). The library never allocates
  *    or frees memory and keeps no state between calls outside the
- *    caller's workspace.
+ *    caller's workspace, except one fault word per device in its static
+ *    device memory (dr_check_device_error).
  *  - Asynchrony: each call only enqueues work on `stream` (NULL = the
  *    default stream) and returns; results are valid once the stream's work
- *    completes. No call synchronises the host except dr_device_status, so
- *    the calls can be captured into a hipGraph.
+ *    completes. No call synchronises the host except dr_device_status and
+ *    dr_check_device_error, so the calls can be captured into a hipGraph.
  *  - Errors: arguments are checked on the host before anything is enqueued;
  *    a failed check returns a negative dr_status and enqueues nothing.
  *    dr_last_error() gives a readable reason (thread-local). Faults that
- *    only the device can see (a malformed device table, a look-back that
- *    never completes, a stale plan) set a flag in the workspace that
- *    dr_device_status reads; the kernels then skip the work instead of
+ *    only the device can see (a malformed device table, a wait that never
+ *    completes, a stale plan) set a flag in the call's workspace, which
+ *    dr_device_status reads, and in a fault word the library keeps per
+ *    device, which dr_check_device_error reads (so calls made without a
+ *    workspace report them too); the kernels then skip the work instead of
  *    touching memory out of range.
  *  - Workspace: a caller-owned device buffer of dr_workspace_bytes bytes,
  *    zero-filled once (dr_workspace_init) before its first use. The kernels
@@ -106,14 +109,16 @@ typedef enum dr_op {
     DR_OP_BLACK_SCHOLES = 4
 } dr_op;
 
-/* Floating-point accumulation of a reduction. PLAIN: binary32 sums inside a
- * tile. COMPENSATED: binary32 (sum, error) pairs with error-free
- * transformations (TwoSum, FMA-based TwoProduct) inside a tile; bfloat16
- * values, squares and products, which are exact in binary32, are summed in
- * binary64 instead (fewer operations, at least as accurate). In both, the
- * tile partials and the combine across tiles and segments are binary64.
- * Integer reductions are always exact in int64 and ignore this setting.
- * binary64 inputs always accumulate in binary64. */
+/* Floating-point accumulation of a reduction of binary32 / bfloat16 inputs.
+ * PLAIN: binary32 sums, per thread over all of its elements, then over the
+ * wave and the workgroup. COMPENSATED: the same in binary32 (sum, error)
+ * pairs built with error-free transformations (TwoSum on every addition,
+ * FMA-based TwoProduct on binary32 products; bfloat16 products and squares
+ * are exact in binary32 and need none), pairs added pairwise (TwoSum of
+ * the sums, errors added). In both, only the workgroup's partial is widened
+ * (exactly) to binary64, and the combine across workgroups and segments is
+ * binary64. Integer reductions are always exact in int64 and ignore this
+ * setting; binary64 inputs accumulate in binary64. */
 typedef enum dr_acc {
     DR_ACC_PLAIN = 0,
     DR_ACC_COMPENSATED = 1
@@ -257,8 +262,10 @@ dr_status dr_plan(const dr_table* table, int32_t algo, const dr_view* view,
  * and no fused multiply-add (the triad a = b + s*c is fl(b + fl(s*c))).
  * Supported (in_dtype -> out_dtype): F32 -> F32, BF16 -> F32, F64 -> F64,
  * I32 -> I32 (two's complement wrap), I32 -> I64.
- * The workspace is needed only for tables larger than DR_SMALL_TABLE
- * (pass NULL/0 otherwise).
+ * The workspace is required for tables larger than DR_SMALL_TABLE (it holds
+ * their plan) and optional otherwise (NULL/0); when one is given, it is
+ * checked as for the other calls and a malformed device table is flagged
+ * in it as well as in the device's fault word (dr_check_device_error).
  */
 dr_status dr_for_each(const dr_table* table, const dr_view* view, int32_t out_dtype,
                       void* workspace, size_t ws_bytes, const dr_tuning* tuning,
@@ -329,7 +336,7 @@ dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view,
  * the derivative is evaluated on in[0], in[1] (mul: d/dx0 = x1,
  * d/dx1 = x0; square: 2*x0; identity: 1; axpy: 1 and alpha), the product is
  * binary64 and rounded once to the output type (= the input type; BF16
- * inputs give F32 gradients).
+ * inputs give F32 gradients). Workspace as dr_for_each.
  */
 dr_status dr_broadcast_mul(const dr_table* table, const dr_view* view, const double* g,
                            int32_t n_grads, void* workspace, size_t ws_bytes,
@@ -449,6 +456,17 @@ dr_status dr_zip_segments(const dr_range* ins, int32_t n_in, const dr_range* out
  * when any bit was set.
  */
 dr_status dr_device_status(void* workspace, uint32_t* flags, void* stream);
+
+/*
+ * Read and clear the fault word the library keeps for the device of
+ * `stream` (NULL = the current device): the DR_DEVFLAG bits (as
+ * dr_device_status) of every fault any kernel of the library flagged on
+ * that device since the last read, including calls made without a
+ * workspace. Synchronises `stream`; *flags (host) receives the bits.
+ * Returns DR_ERR_DEVICE when any bit was set. The word is shared by every
+ * caller on the device: concurrent callers see each other's faults.
+ */
+dr_status dr_check_device_error(uint32_t* flags, void* stream);
 
 #ifdef __cplusplus
 }

@@ -82,7 +82,8 @@ assert ctypes.sizeof(dr_view) == 24
 EXPORTS = ["dr_abi_version", "dr_status_string", "dr_last_error", "dr_tuning_supported",
            "dr_workspace_bytes", "dr_workspace_init", "dr_plan", "dr_for_each",
            "dr_transform_reduce", "dr_inclusive_scan", "dr_scan_reduce", "dr_broadcast_mul",
-           "dr_device_status", "dr_trim_segments", "dr_zip_segments", "dr_reduce", "dr_scan"]
+           "dr_device_status", "dr_trim_segments", "dr_zip_segments", "dr_reduce", "dr_scan",
+           "dr_check_device_error"]
 
 _lib = None
 
@@ -118,6 +119,7 @@ def lib() -> ctypes.CDLL:
     L.dr_scan_reduce.argtypes = [TP, VP, VP, i32, P, P, u32, P, S, UP, P]
     L.dr_broadcast_mul.argtypes = [TP, VP, P, i32, P, S, UP, P]
     L.dr_device_status.argtypes = [P, ctypes.POINTER(u32), P]
+    L.dr_check_device_error.argtypes = [ctypes.POINTER(u32), P]
     L.dr_reduce.argtypes = [TP, VP, i32, i32, P, P, P, S, UP, P]
     L.dr_scan.argtypes = [TP, VP, i32, i32, u32, P, P, S, UP, P]
     RP, I64P = ctypes.POINTER(dr_range), ctypes.POINTER(i64)
@@ -311,13 +313,10 @@ def _tp(tuning):
 
 def dr_for_each(table: Table, view: dr_view, out_dtype: int, workspace: Workspace | None = None,
                 tuning: dr_tuning | None = None, host_check: bool = True) -> None:
+    workspace = workspace or default_workspace(table.device)
+    workspace.for_call(DR_ALGO_FOR_EACH, table, view, tuning)
     c = table.c_table(host_check)
-    ws_ptr, ws_n = 0, 0
-    if table.n_segments > DR_SMALL_TABLE:
-        workspace = workspace or default_workspace(table.device)
-        workspace.for_call(DR_ALGO_FOR_EACH, table, view, tuning)
-        ws_ptr, ws_n = workspace.ptr, workspace.nbytes
-    check(lib().dr_for_each(ctypes.byref(c), ctypes.byref(view), out_dtype, ws_ptr or None, ws_n,
+    check(lib().dr_for_each(ctypes.byref(c), ctypes.byref(view), out_dtype, workspace.ptr, workspace.nbytes,
                             _tp(tuning), _stream(table.device)))
 
 
@@ -389,19 +388,27 @@ def dr_broadcast_mul(table: Table, view: dr_view, g: torch.Tensor, n_grads: int,
                      host_check: bool = True) -> None:
     if g.dtype != torch.float64 or not g.is_contiguous():
         raise TypeError("g must be a contiguous float64 device tensor")
+    workspace = workspace or default_workspace(table.device)
+    workspace.for_call(DR_ALGO_BROADCAST_MUL, table, view, tuning)
     c = table.c_table(host_check)
-    ws_ptr, ws_n = 0, 0
-    if table.n_segments > DR_SMALL_TABLE:
-        workspace = workspace or default_workspace(table.device)
-        workspace.for_call(DR_ALGO_BROADCAST_MUL, table, view, tuning)
-        ws_ptr, ws_n = workspace.ptr, workspace.nbytes
     check(lib().dr_broadcast_mul(ctypes.byref(c), ctypes.byref(view), g.data_ptr(), n_grads,
-                                 ws_ptr or None, ws_n, _tp(tuning), _stream(table.device)))
+                                 workspace.ptr, workspace.nbytes, _tp(tuning), _stream(table.device)))
 
 
 def dr_device_status(workspace: Workspace) -> int:
     """Raw device fault flags of the workspace (0 = none); clears them."""
     return workspace.device_status()
+
+
+def dr_check_device_error(device=None) -> int:
+    """Raw bits of the device's library-wide fault word (0 = none), covering
+    every call on the device, with or without a workspace; clears them."""
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    flags = ctypes.c_uint32(0)
+    st = lib().dr_check_device_error(ctypes.byref(flags), _stream(device))
+    if st not in (DR_OK, DR_ERR_DEVICE):
+        check(st)
+    return int(flags.value)
 
 
 # --- segment algebra (section 4.4): take / drop and zip of non-aligned ranges ----

@@ -73,14 +73,11 @@ int default_items(int algo, int in_dt) {
 }
 
 // Bound of the wait loops, in wall-clock ticks (about 2.7 s at 100 MHz);
-// DR_SPIN_TICKS overrides it (tests of the timeout path).
+// DR_SPIN_TICKS overrides it (tests of the timeout path), read at every call.
 uint64_t spin_ticks() {
-    static uint64_t v = [] {
-        const char* e = std::getenv("DR_SPIN_TICKS");
-        if (e && *e) return (uint64_t)std::strtoull(e, nullptr, 10);
-        return (uint64_t)1 << 28;
-    }();
-    return v;
+    const char* e = std::getenv("DR_SPIN_TICKS");
+    if (e && *e) return (uint64_t)std::strtoull(e, nullptr, 10);
+    return (uint64_t)1 << 28;
 }
 
 dr_status check_view(const dr_view* v, bool int_ok) {
@@ -241,8 +238,8 @@ dr_status prepare(const dr_table* t, int algo, int in_dt, int out_dt, int arity,
     if (tmax >= ((int64_t)1 << 31)) return fail(DR_ERR_UNSUPPORTED, "too many tiles (%lld)", (long long)tmax);
     const WsLayout lay = layout_for(algo, t->n_segments, tmax);
     const bool need_ws = ws_required || t->n_segments > DR_SMALL_TABLE;
-    if (need_ws) {
-        if (!ws) return fail(DR_ERR_WORKSPACE, "a workspace is required");
+    if (need_ws && !ws) return fail(DR_ERR_WORKSPACE, "a workspace is required");
+    if (ws) {   // an optional workspace, once given, is used and checked like a required one
         if ((uintptr_t)ws % 256) return fail(DR_ERR_WORKSPACE, "workspace must be 256-byte aligned");
         if (ws_bytes < lay.bytes)
             return fail(DR_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %llu needed", ws_bytes,
@@ -279,7 +276,19 @@ int dr::resident_grid(const void* kernel, int threads) {
 
 namespace {
 
-dr_status launch(LaunchFn fn, const Prepared& p, void* stream, const char* what) {
+// The device fault word of the stream's device (the first HIP call of an
+// entry point: every host-side check has passed by then).
+dr_status bind_device(Prepared& p, void* stream) {
+    DeviceGlobals dg;
+    const hipError_t e = device_globals((hipStream_t)stream, dg);
+    if (e != hipSuccess) return hip_fail(e, "device fault word lookup");
+    p.a.gfault = dg.fault;
+    return DR_OK;
+}
+
+dr_status launch(LaunchFn fn, Prepared& p, void* stream, const char* what) {
+    dr_status s = bind_device(p, stream);
+    if (s) return s;
     hipError_t e = fn(p.a, p.grid, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, what);
     return ok();
@@ -360,6 +369,8 @@ dr_status dr_plan(const dr_table* table, int32_t algo, const dr_view* view, cons
                 items);
     if (s) return s;
     if (table->n_segments <= DR_SMALL_TABLE) return ok();   // planned inside every launch
+    s = bind_device(p, stream);
+    if (s) return s;
     hipError_t e = launch_plan(p.a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "plan");
     return ok();
@@ -653,6 +664,27 @@ dr_status dr_broadcast_mul(const dr_table* table, const dr_view* view, const dou
     p.a.alpha = view->alpha;
     p.a.g = g;
     return launch(fn, p, stream, "broadcast_mul launch");
+}
+
+dr_status dr_check_device_error(uint32_t* flags, void* stream) {
+    if (!flags) return fail(DR_ERR_INVALID_ARG, "flags is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    DeviceGlobals dg;
+    hipError_t e = device_globals(st, dg);
+    if (e != hipSuccess) return hip_fail(e, "device fault word lookup");
+    uint32_t host = 0;
+    e = hipMemcpyAsync(&host, dg.fault, sizeof host, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "device fault word read");
+    *flags = host;
+    if (host != 0) {
+        const uint32_t zero = 0;
+        e = hipMemcpyAsync(dg.fault, &zero, sizeof zero, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "device fault word clear");
+        return fail(DR_ERR_DEVICE, "device fault flags 0x%x", host);
+    }
+    return ok();
 }
 
 dr_status dr_device_status(void* ws, uint32_t* flags, void* stream) {

@@ -38,7 +38,7 @@ __device__ __forceinline__ P wait_tagged(const LaunchArgs& a, const uint64_t* w,
         Deadline dl(a.spin_ticks);
         while (!tagged_load(w, tag, bitsv)) {
             if (dl.passed()) {
-                flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
+                flag_error(a, DR_DEVFLAG_TIMEOUT);
                 bitsv = 0;
                 break;
             }

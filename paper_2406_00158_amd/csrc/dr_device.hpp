@@ -284,39 +284,86 @@ __device__ __forceinline__ void comp_accumulate(const vec<IDT> (&x)[SLOTS], cons
     }
 }
 
-// The compensated sum of the view over a thread's elements, as binary64.
-// bfloat16 values, squares and products are exact in binary32 (at most 16
-// significant bits), so they are summed in binary64 instead of in TwoSum
-// pairs: two operations per element instead of TwoSum's six, and the sum is
-// exact until it needs more than 53 significant bits. Two accumulators (even
-// and odd elements) shorten the dependency chain; the order is fixed.
-// Otherwise the (sum, error) pair of comp_accumulate, joined in binary64
-// (exactly, unless the sum is not finite).
+// Plain binary32 accumulation of the view values into s (one rounding per
+// operation; the product of a mul view is rounded before the sum).
 template <int IDT, int OP, int SLOTS>
-__device__ __forceinline__ double comp_partial(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS], float alpha) {
+__device__ __forceinline__ void plain_accumulate(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS], float alpha,
+                                                 float& s) {
     constexpr int V = vwidth<IDT>();
-    if constexpr (IDT == DR_BF16 && (OP == DR_OP_IDENTITY || OP == DR_OP_SQUARE || OP == DR_OP_MUL)) {
-        double s0 = 0.0, s1 = 0.0;
+    constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
 #pragma unroll
-        for (int q = 0; q < SLOTS; ++q) {
+    for (int q = 0; q < SLOTS; ++q) {
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const float x0 = decode<IDT>(x[q].e[e]);
-                float p;
-                if constexpr (OP == DR_OP_IDENTITY) p = x0;
-                else if constexpr (OP == DR_OP_SQUARE) p = x0 * x0;
-                else p = x0 * decode<IDT>(y[q].e[e]);
-                if (e & 1) s1 += (double)p;
-                else s0 += (double)p;
+        for (int e = 0; e < V; ++e) {
+            const float x0 = decode<IDT>(x[q].e[e]);
+            const float x1 = ZIP ? decode<IDT>(y[q].e[e]) : 0.0f;
+            float v;
+            if constexpr (OP == DR_OP_IDENTITY) v = x0;
+            else if constexpr (OP == DR_OP_SQUARE) v = x0 * x0;
+            else if constexpr (OP == DR_OP_MUL) v = x0 * x1;
+            else {
+                const float t = alpha * x1;
+                v = x0 + t;
             }
+            s += v;
         }
-        (void)alpha;
-        return s0 + s1;
-    } else {
-        float s = 0.0f, c = 0.0f;
-        comp_accumulate<IDT, OP, SLOTS>(x, y, alpha, s, c);
-        return __builtin_isfinite(s) ? (double)s + (double)c : (double)s;
     }
+}
+
+// (s, c) += (s2, c2) for compensated pairs: TwoSum of the two sums, and the
+// new rounding error with both error terms into c, in a fixed order.
+__device__ __forceinline__ void pair_add(float& s, float& c, float s2, float c2) {
+    float e;
+    two_sum(s, s2, s, e);
+    c = c + (c2 + e);
+}
+
+// Sum of the lanes' compensated pairs over the wave, over a fixed tree
+// (pair_add at every level; lanes without a partner add (0, 0), exactly);
+// the result in every lane.
+__device__ __forceinline__ void wave_sum_pair(float& s, float& c) {
+    pair_add(s, c, dpp_move<DPP_ROW_SHR1, 0xf>(s), dpp_move<DPP_ROW_SHR1, 0xf>(c));
+    pair_add(s, c, dpp_move<DPP_ROW_SHR2, 0xf>(s), dpp_move<DPP_ROW_SHR2, 0xf>(c));
+    pair_add(s, c, dpp_move<DPP_ROW_SHR4, 0xf>(s), dpp_move<DPP_ROW_SHR4, 0xf>(c));
+    pair_add(s, c, dpp_move<DPP_ROW_SHR8, 0xf>(s), dpp_move<DPP_ROW_SHR8, 0xf>(c));
+    pair_add(s, c, dpp_move<DPP_ROW_BCAST15, 0xa>(s), dpp_move<DPP_ROW_BCAST15, 0xa>(c));
+    pair_add(s, c, dpp_move<DPP_ROW_BCAST31, 0xc>(s), dpp_move<DPP_ROW_BCAST31, 0xc>(c));
+    s = readlane(s, 63);
+    c = readlane(c, 63);
+}
+
+// A compensated pair widened to binary64 (s + c, exact unless the
+// exponents of s and c are more than 29 apart; a non-finite sum is
+// returned as is).
+__device__ __forceinline__ double pair_widen(float s, float c) {
+    return __builtin_isfinite(s) ? (double)s + (double)c : (double)s;
+}
+
+// Partial of a workgroup of WAVES waves in binary64, from the per-thread
+// binary32 accumulators: the waves' sums (compensated pairs or plain
+// sums), then the waves in order in thread 0, all in binary32; only the
+// workgroup's result is widened. Every thread must call it; the result is
+// valid in thread 0. `sp`/`cp` are WAVES floats of LDS each.
+template <bool COMP, int WAVES>
+__device__ __forceinline__ double block_partial_f32(float s, float c, float* sp, float* cp) {
+    const int w = threadIdx.x >> 6;
+    if constexpr (COMP) wave_sum_pair(s, c);
+    else s = readlane(wave_incl_scan(s), 63);
+    if (lane_id() == 0) {
+        sp[w] = s;
+        if constexpr (COMP) cp[w] = c;
+    }
+    __syncthreads();
+    double part = 0.0;
+    if (threadIdx.x == 0) {
+        float ts = sp[0], tc = COMP ? cp[0] : 0.0f;
+        for (int i = 1; i < WAVES; ++i) {
+            if constexpr (COMP) pair_add(ts, tc, sp[i], cp[i]);
+            else ts += sp[i];
+        }
+        part = COMP ? pair_widen(ts, tc) : (double)ts;
+    }
+    return part;
 }
 
 // ---------------------------------------------------------------------------
@@ -380,8 +427,12 @@ __device__ __forceinline__ uint32_t epoch_tag(uint32_t epoch) {
     return (epoch % 0xFFFFFFFEu) + 1u;   // never 0 (fresh workspace) nor ~0
 }
 
-__device__ __forceinline__ void flag_error(uint8_t* ws, uint32_t bit) {
-    if (ws != nullptr) atomic_or32(&header(ws)->error, bit);
+// Record a device-detected fault: in the launch's workspace (when it has
+// one) and in the device's library-wide fault word, so that a call made
+// without a workspace can report it too (dr_check_device_error).
+__device__ __forceinline__ void flag_error(const LaunchArgs& a, uint32_t bit) {
+    if (a.ws != nullptr) atomic_or32(&header(a.ws)->error, bit);
+    if (a.gfault != nullptr) atomic_or32(a.gfault, bit);
 }
 
 // Tag of the running launch: the prologue kernel that precedes every
@@ -537,7 +588,7 @@ struct TileMap {
             ok = !anybad && nsum == a.total && total_tiles <= a.tmax;
             if (!ok) {
                 if (threadIdx.x == 0)
-                    flag_error(a.ws, (anybad || nsum != a.total) ? DR_DEVFLAG_BAD_TABLE
+                    flag_error(a, (anybad || nsum != a.total) ? DR_DEVFLAG_BAD_TABLE
                                                                  : DR_DEVFLAG_TOO_MANY_TILES);
                 total_tiles = 0;
             }
@@ -549,12 +600,12 @@ struct TileMap {
              ld_const(&h->plan_ies) == a.ies && ld_const(&h->plan_total) == a.total;
         plan_tag = ok ? ld_const(&h->plan_tag) : 0u;
         if (!ok) {
-            if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_PLAN);
+            if (threadIdx.x == 0) flag_error(a, DR_DEVFLAG_PLAN);
             return;
         }
         total_tiles = ld_const(&h->plan_tiles);
         if (total_tiles > a.tmax) {
-            if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_TOO_MANY_TILES);
+            if (threadIdx.x == 0) flag_error(a, DR_DEVFLAG_TOO_MANY_TILES);
             total_tiles = 0;
             ok = false;
         }
@@ -580,7 +631,7 @@ struct TileMap {
             const bool kok = (uint32_t)(wk >> 32) == plan_tag && (int64_t)kk < a.m;
             const uint64_t f0 = kok ? ld_const(F + kk) : 0, f1 = kok ? ld_const(F + kk + 1) : 0;
             if (!kok || (uint32_t)(f0 >> 32) != plan_tag || (uint32_t)(f1 >> 32) != plan_tag) {
-                if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_PLAN);
+                if (threadIdx.x == 0) flag_error(a, DR_DEVFLAG_PLAN);
                 return false;
             }
             k = (int)kk;
@@ -588,7 +639,7 @@ struct TileMap {
             si.ntiles = (int64_t)(uint32_t)f1 - (int64_t)(uint32_t)f0;
             const Row r = load_row(a.rows, k);
             if (row_bad(r, a.arity, a.nout)) {
-                if (threadIdx.x == 0) flag_error(a.ws, DR_DEVFLAG_BAD_TABLE);
+                if (threadIdx.x == 0) flag_error(a, DR_DEVFLAG_BAD_TABLE);
                 return false;
             }
             si.n = r.n;

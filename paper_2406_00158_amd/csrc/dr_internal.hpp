@@ -81,6 +81,7 @@ struct LaunchArgs {
     int64_t init_i;
     const double* g;
     uint64_t spin_ticks;  // bound of every wait, wall-clock ticks
+    uint32_t* gfault;     // the device's library-wide fault word (device address)
 };
 
 // Launches the kernel with `grid` workgroups, one per tile (kernels that use
@@ -118,6 +119,17 @@ LaunchFn find_broadcast_mul(int in_dt, int op, int items);
 LaunchFn find_black_scholes(int items);
 hipError_t launch_plan(const LaunchArgs& a, hipStream_t stream);     // prefix + tile -> segment map
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);  // fill with 0 (graph safe)
+
+// Device addresses of the library's static device memory on the device of
+// `stream`: the fault word every kernel also reports to, and the scratch
+// area of the calls that allocate nothing. Looked up once per device.
+struct DeviceGlobals {
+    uint32_t* fault;
+    uint8_t* scratch;
+    size_t scratch_bytes;
+    int device;
+};
+hipError_t device_globals(hipStream_t stream, DeviceGlobals& g);
 
 
 }  // namespace dr

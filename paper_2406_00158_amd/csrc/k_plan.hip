@@ -69,9 +69,9 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_prefix(LaunchArgs a) {
     if (threadIdx.x == 0) {
         F[a.m] = ((uint64_t)tag << 32) | (uint64_t)s_carry;
         if (s_bad || s_len != a.total) {
-            flag_error(a.ws, DR_DEVFLAG_BAD_TABLE);
+            flag_error(a, DR_DEVFLAG_BAD_TABLE);
         } else if (s_carry > a.tmax) {
-            flag_error(a.ws, DR_DEVFLAG_TOO_MANY_TILES);
+            flag_error(a, DR_DEVFLAG_TOO_MANY_TILES);
         } else {
             h->plan_rows = (uint64_t)(uintptr_t)a.rows;
             h->plan_tile = a.tile;

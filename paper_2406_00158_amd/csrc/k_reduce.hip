@@ -10,16 +10,21 @@
 // in BATCH mode. No second pass, no host-side combine, and no atomic that
 // every workgroup hits (a one-thread prologue bumps the launch epoch).
 //
-// Accumulation inside a tile:
+// Accumulation inside a workgroup (over its tile, or in the streaming form
+// over all of its tiles):
 //  - int32 inputs: int64, exact.
-//  - binary32 / bfloat16 inputs, PLAIN: binary32 running sums and a
-//    binary32 tree; the tile partial is widened to binary64.
+//  - binary32 / bfloat16 inputs, PLAIN: binary32 running sums per thread, a
+//    binary32 tree over the wave and the waves in order, all in binary32;
+//    only the workgroup's partial is widened to binary64.
 //  - COMPENSATED: a binary32 (sum, error) pair per thread: TwoSum (Knuth) on
-//    every addition and an FMA-based TwoProduct for products, which keeps
-//    each rounding error of the binary32 arithmetic. The pair is widened to
-//    binary64 (exactly) at the end of the tile and the tree runs in binary64.
+//    every addition and an FMA-based TwoProduct for products (bfloat16
+//    products are exact in binary32 and need none), which keeps each
+//    rounding error of the binary32 arithmetic; the pairs are added pairwise
+//    (TwoSum of the sums, errors added) over the wave and the waves, still in
+//    binary32, and only the workgroup's pair is widened (exactly) to binary64.
 //  - binary64 inputs: binary64 sums.
-// Partials are combined across tiles and segments in binary64 (or int64).
+// Workgroup partials are combined across workgroups and segments in binary64
+// (or int64): the only binary64 arithmetic of a binary32 reduction.
 #include "dr_combine.hpp"
 
 namespace dr {
@@ -71,6 +76,27 @@ __device__ __forceinline__ partial_t<IDT> thread_tile_minmax(const vec<IDT> (&x)
     }
 }
 
+// Exact (int64) or binary64 sum of the view over a thread's loaded
+// elements (int32 and binary64 inputs).
+template <int IDT, int OP, int SLOTS>
+__device__ __forceinline__ partial_t<IDT> thread_tile_exact(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS],
+                                                           double alpha_d) {
+    constexpr int V = vwidth<IDT>();
+    constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
+    using P = partial_t<IDT>;
+    const P alpha = (P)alpha_d;
+    P acc = (P)0;
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const P x1 = ZIP ? (P)decode<IDT>(y[q].e[e]) : (P)0;
+            acc += view_apply<OP, P>((P)decode<IDT>(x[q].e[e]), x1, alpha);
+        }
+    }
+    return acc;
+}
+
 // Sum of the view over one tile, returned in thread 0 (whole workgroup).
 template <int IDT, int OP, int ACC, int ITEMS>
 __device__ __forceinline__ partial_t<IDT> tile_partial(const LaunchArgs& a, const SegInfo& si, int64_t t) {
@@ -81,7 +107,7 @@ __device__ __forceinline__ partial_t<IDT> tile_partial(const LaunchArgs& a, cons
     using P = partial_t<IDT>;
     constexpr bool F32PATH = (IDT == DR_F32 || IDT == DR_BF16);
     __shared__ P s_wave[WAVES];
-    __shared__ float s_wavef[WAVES];
+    __shared__ float s_ws[WAVES], s_wc[WAVES];
 
     const int w = threadIdx.x >> 6, l = lane_id();
     const int64_t u0 = (t - si.first) * a.tile;
@@ -99,48 +125,15 @@ __device__ __forceinline__ partial_t<IDT> tile_partial(const LaunchArgs& a, cons
             part = mm_id<P>(mn);
             for (int i = 0; i < WAVES; ++i) part = mm_op(part, s_wave[i], mn);
         }
-    } else if constexpr (F32PATH && ACC == DR_ACC_COMPENSATED) {
-        const P tp = comp_partial<IDT, OP, SLOTS>(x, y, (float)a.alpha);
-        const P wsum = wave_sum(tp);
-        if (l == 0) s_wave[w] = wsum;
-        __syncthreads();
-        if (threadIdx.x == 0)
-            for (int i = 0; i < WAVES; ++i) part += s_wave[i];
     } else if constexpr (F32PATH) {
-        const float alpha = (float)a.alpha;
-        float acc = 0.0f;
-#pragma unroll
-        for (int q = 0; q < SLOTS; ++q) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const float x0 = decode<IDT>(x[q].e[e]);
-                const float x1 = ZIP ? decode<IDT>(y[q].e[e]) : 0.0f;
-                acc += view_apply<OP, float>(x0, x1, alpha);
-            }
-        }
-        const float wsum = wave_sum(acc);
-        if (l == 0) s_wavef[w] = wsum;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float pf = 0.0f;
-            for (int i = 0; i < WAVES; ++i) pf += s_wavef[i];
-            part = (double)pf;
-        }
+        constexpr bool COMP = ACC == DR_ACC_COMPENSATED;
+        float fs = 0.0f, fc = 0.0f;
+        if constexpr (COMP) comp_accumulate<IDT, OP, SLOTS>(x, y, (float)a.alpha, fs, fc);
+        else plain_accumulate<IDT, OP, SLOTS>(x, y, (float)a.alpha, fs);
+        part = block_partial_f32<COMP, WAVES>(fs, fc, s_ws, s_wc);
     } else {
         // int32 -> int64 exact, or binary64
-        using A = P;
-        const A alpha = (A)a.alpha;
-        A acc = (A)0;
-#pragma unroll
-        for (int q = 0; q < SLOTS; ++q) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const A x0 = (A)decode<IDT>(x[q].e[e]);
-                const A x1 = ZIP ? (A)decode<IDT>(y[q].e[e]) : (A)0;
-                acc += view_apply<OP, A>(x0, x1, alpha);
-            }
-        }
-        const A wsum = wave_sum(acc);
+        const P wsum = wave_sum(thread_tile_exact<IDT, OP, SLOTS>(x, y, a.alpha));
         if (l == 0) s_wave[w] = wsum;
         __syncthreads();
         if (threadIdx.x == 0)
@@ -173,50 +166,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce(LaunchArgs a) {
     }
 }
 
-// Per-thread sum of one tile's elements (already in registers), widened to
-// the partial type. COMPENSATED: binary32 (sum, error) pair over the tile,
-// then widened exactly; PLAIN: binary32 running sum, widened.
-template <int IDT, int OP, int ACC, int SLOTS>
-__device__ __forceinline__ partial_t<IDT> thread_tile_sum(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS],
-                                                         double alpha_d) {
-    constexpr int V = vwidth<IDT>();
-    constexpr bool ZIP = (OP == DR_OP_MUL || OP == DR_OP_AXPY);
-    using P = partial_t<IDT>;
-    if constexpr ((IDT == DR_F32 || IDT == DR_BF16) && ACC == DR_ACC_COMPENSATED) {
-        return comp_partial<IDT, OP, SLOTS>(x, y, (float)alpha_d);
-    } else if constexpr (IDT == DR_F32 || IDT == DR_BF16) {
-        const float alpha = (float)alpha_d;
-        float acc = 0.0f;
-#pragma unroll
-        for (int q = 0; q < SLOTS; ++q) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const float x1 = ZIP ? decode<IDT>(y[q].e[e]) : 0.0f;
-                acc += view_apply<OP, float>(decode<IDT>(x[q].e[e]), x1, alpha);
-            }
-        }
-        return (double)acc;
-    } else {
-        const P alpha = (P)alpha_d;
-        P acc = (P)0;
-#pragma unroll
-        for (int q = 0; q < SLOTS; ++q) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const P x1 = ZIP ? (P)decode<IDT>(y[q].e[e]) : (P)0;
-                acc += view_apply<OP, P>((P)decode<IDT>(x[q].e[e]), x1, alpha);
-            }
-        }
-        return acc;
-    }
-}
-
 // CONCAT streaming form: a grid of resident workgroups, workgroup b taking
 // tiles b, b + G, b + 2G, ... with the loads of its next tile in flight while
-// it sums the current one. Each thread keeps a binary64 (int64) sum over its
-// tiles; the workgroup publishes one partial and the partials of the G
-// workgroups are combined in workgroup order. The tile-to-workgroup map is
-// fixed for a given grid, so the result is the same from run to run.
+// it sums the current one. Each thread accumulates all of its elements in
+// binary32 (a compensated pair, or a plain sum; int64 / binary64 for int32 /
+// binary64 inputs), the workgroup reduces its threads in binary32 and
+// publishes one binary64 partial, and the partials of the G workgroups are
+// combined in workgroup order. The tile-to-workgroup map is fixed for a
+// given grid, so the result is the same from run to run.
 template <int IDT, int OP, int ACC, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_reduce_stream(LaunchArgs a) {
     constexpr int V = vwidth<IDT>();
@@ -225,7 +182,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stream(LaunchArgs a) {
     constexpr int WAVES = kBlock / 64;
     using P = partial_t<IDT>;
     constexpr int CMB = ACC == kAccMinMax ? kCmbMinMax : kCmbSum;
+    constexpr bool F32PATH = (IDT == DR_F32 || IDT == DR_BF16) && CMB == kCmbSum;
+    constexpr bool COMP = ACC == DR_ACC_COMPENSATED;
     __shared__ P s_wave[WAVES];
+    __shared__ float s_ws[WAVES], s_wc[WAVES];
     const uint32_t tag = begin_launch(a.ws);
     TileMap tm;
     tm.init(a);
@@ -234,14 +194,19 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stream(LaunchArgs a) {
     const int64_t G = gridDim.x;
     const int w = threadIdx.x >> 6, l = lane_id();
     const bool mn = (a.flags & kFlagMin) != 0;
-    // the thread's partial over its tiles: a binary64 / int64 sum, or max / min
-    auto merge = [&](P acc, const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS], const SegInfo& si,
-                     int64_t tt) -> P {
-        if constexpr (CMB == kCmbMinMax)
-            return mm_op(acc, thread_tile_minmax<IDT, OP, SLOTS>(x, y, a.alpha, mn, si, (tt - si.first) * a.tile), mn);
-        else return acc + thread_tile_sum<IDT, OP, ACC, SLOTS>(x, y, a.alpha);
-    };
+    const float alpha_f = (float)a.alpha;
+    // the thread's accumulators over its tiles: binary32 (fs, fc), or a
+    // binary64 / int64 sum, or max / min
+    float fs = 0.0f, fc = 0.0f;
     P mine = cmb_id<CMB, P>(mn);
+    auto merge = [&](const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS], const SegInfo& si, int64_t tt) {
+        if constexpr (CMB == kCmbMinMax)
+            mine = mm_op(mine, thread_tile_minmax<IDT, OP, SLOTS>(x, y, a.alpha, mn, si, (tt - si.first) * a.tile),
+                         mn);
+        else if constexpr (F32PATH && COMP) comp_accumulate<IDT, OP, SLOTS>(x, y, alpha_f, fs, fc);
+        else if constexpr (F32PATH) plain_accumulate<IDT, OP, SLOTS>(x, y, alpha_f, fs);
+        else mine += thread_tile_exact<IDT, OP, SLOTS>(x, y, a.alpha);
+    };
     vec<IDT> xa[SLOTS], ya[SLOTS], xb[SLOTS], yb[SLOTS];
     int64_t t = blockIdx.x;
     SegInfo sa, sb;
@@ -257,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stream(LaunchArgs a) {
             load_slots<IDT, SLOTS>(xb, sb.in0, sb, (tb - sb.first) * a.tile, w, l, false);
             if constexpr (ZIP) load_slots<IDT, SLOTS>(yb, sb.in1, sb, (tb - sb.first) * a.tile, w, l, false);
         }
-        mine = merge(mine, xa, ya, sa, t);
+        merge(xa, ya, sa, t);
         if (!hb) break;
         const int64_t ta = tb + G;
         ha = ta < T && tm.find(a, ta, sa);
@@ -265,16 +230,21 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stream(LaunchArgs a) {
             load_slots<IDT, SLOTS>(xa, sa.in0, sa, (ta - sa.first) * a.tile, w, l, false);
             if constexpr (ZIP) load_slots<IDT, SLOTS>(ya, sa.in1, sa, (ta - sa.first) * a.tile, w, l, false);
         }
-        mine = merge(mine, xb, yb, sb, tb);
+        merge(xb, yb, sb, tb);
         t = ta;
     }
-    const P wsum = wave_reduce_cmb<CMB>(mine, mn);
-    if (l == 0) s_wave[w] = wsum;
-    __syncthreads();
-    if (threadIdx.x >= 64) return;
     P part = cmb_id<CMB, P>(mn);
-    if (l == 0)
-        for (int i = 0; i < WAVES; ++i) part = cmb_op<CMB>(part, s_wave[i], mn);
+    if constexpr (F32PATH) {
+        part = (P)block_partial_f32<COMP, WAVES>(fs, fc, s_ws, s_wc);
+        if (threadIdx.x >= 64) return;
+    } else {
+        const P wsum = wave_reduce_cmb<CMB>(mine, mn);
+        if (l == 0) s_wave[w] = wsum;
+        __syncthreads();
+        if (threadIdx.x >= 64) return;
+        if (l == 0)
+            for (int i = 0; i < WAVES; ++i) part = cmb_op<CMB>(part, s_wave[i], mn);
+    }
     combine_member<P, CMB>(a, tag, 0, 0, blockIdx.x, G, 0, part);
 }
 

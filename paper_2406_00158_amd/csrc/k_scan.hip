@@ -1,18 +1,26 @@
-// k_scan.hip — single-pass inclusive_scan over a zip/transform view of a
-// segmented range (section 4.3, "inclusive_scan"; Algorithm 4), and its
-// fusion with a transform_reduce over the same rows.
+// k_scan.hip — inclusive_scan over a zip/transform view of a segmented
+// range (section 4.3, "inclusive_scan"; Algorithm 4), and its fusion with a
+// transform_reduce over the same rows.
 //
 // The paper scans each segment locally, scans the segment totals, then adds
-// each segment's offset in a second pass over the data (the extra pass it
-// blames for the scan's drop from one to two tiles, section 5.1). Here the
-// offsets never take a second pass: one workgroup per tile, in block-index
-// order, scans its elements in registers, publishes its aggregate, and wave
-// 0 looks back over its predecessors' published
-// aggregates / inclusive prefixes (Merrill & Garland, "Single-pass Parallel
-// Prefix Scan with Decoupled Look-back", 2016) to get the tile's exclusive
-// carry. The look-back runs across segment boundaries in CONCAT mode (the
-// carry of segment k is the total of segments before it) and stops at the
-// segment's first tile in BATCH mode. Results are written once.
+// each segment's offset in a second read-write pass over the data (the
+// extra pass it blames for the scan's drop from one to two tiles, section
+// 5.1). Three forms are built here; every one writes each output once:
+//  - reduce-then-scan (the default): a read-only pass forms every tile's
+//    total, one small kernel scans the per-chunk totals, and the apply pass
+//    re-reads the input, scans each tile in registers and adds its carry
+//    (the input is read twice; carries are sums in a fixed order);
+//  - decoupled look-back (DR_TUNE_TILE_PER_BLOCK; Merrill & Garland,
+//    "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016): one
+//    workgroup per tile, in block-index order, publishes its aggregate and
+//    looks back over its predecessors' aggregates / inclusive prefixes for
+//    its carry;
+//  - specialised waves (DR_TUNE_SPECIALIZED): one pass with loader, writer,
+//    publisher and carry-fetcher waves per workgroup and one workgroup that
+//    scans the published tile totals in a fixed order.
+// Carries cross segment boundaries in CONCAT mode (the carry of segment k
+// is the total of the segments before it) and restart at every segment's
+// first tile in BATCH mode.
 //
 // Precision: int32 inputs scan in int64 (exact). binary32 / bfloat16
 // inputs scan in binary32 inside a tile; the carries between tiles are
@@ -91,7 +99,7 @@ __device__ __forceinline__ C look_back(const LaunchArgs& a, uint32_t tag, int64_
         }
         __syncthreads();
         if (s_timeout) {
-            if (tid == 0) flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
+            if (tid == 0) flag_error(a, DR_DEVFLAG_TIMEOUT);
             break;
         }
         // 2. one read of the statuses of up to 256 predecessors
@@ -188,34 +196,52 @@ __device__ __forceinline__ typename elem<ODT>::T scan_out_cmb(carry_t<IDT, C64> 
     }
 }
 
-// Per-thread sum of ROP over the zipped (in0, in1) elements of a loaded
-// tile, accumulated as RACC (the fused reduction; order-insensitive, so it
-// is taken before the scan values replace the loaded ones).
+// Per-wave partial of the fused reduction (ROP over the zipped (in0, in1)
+// elements of a loaded tile, accumulated as RACC; order-insensitive, so it
+// is taken before the scan values replace the loaded ones): binary32 inputs
+// in binary32 (a compensated pair, or a plain sum), binary64 inputs in
+// binary64. The result is in every lane.
 template <int IDT, int ROP, int RACC, int SLOTS>
-__device__ __forceinline__ double fused_partial(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS]) {
+__device__ __forceinline__ void fused_wave(const vec<IDT> (&x)[SLOTS], const vec<IDT> (&y)[SLOTS], float& s,
+                                           float& c, double& d) {
     constexpr int V = vwidth<IDT>();
+    s = 0.0f;
+    c = 0.0f;
+    d = 0.0;
     if constexpr (IDT == DR_F64) {
         double rs = 0.0;
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
+        for (int q = 0; q < SLOTS; ++q) {
 #pragma unroll
             for (int e = 0; e < V; ++e)
-                rs += view_apply<ROP, double>(decode<IDT>(x[s].e[e]), decode<IDT>(y[s].e[e]), 0.0);
+                rs += view_apply<ROP, double>(decode<IDT>(x[q].e[e]), decode<IDT>(y[q].e[e]), 0.0);
         }
-        return rs;
+        d = wave_sum(rs);
+    } else if constexpr (RACC == DR_ACC_COMPENSATED) {
+        comp_accumulate<IDT, ROP, SLOTS>(x, y, 0.0f, s, c);
+        wave_sum_pair(s, c);
     } else {
-        if constexpr (RACC == DR_ACC_COMPENSATED) {
-            return comp_partial<IDT, ROP, SLOTS>(x, y, 0.0f);
-        } else {
-            float rs = 0.0f;
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-#pragma unroll
-                for (int e = 0; e < V; ++e)
-                    rs += view_apply<ROP, float>((float)decode<IDT>(x[s].e[e]), (float)decode<IDT>(y[s].e[e]), 0.0f);
-            }
-            return (double)rs;
-        }
+        plain_accumulate<IDT, ROP, SLOTS>(x, y, 0.0f, s);
+        s = readlane(wave_incl_scan(s), 63);
+    }
+}
+
+// The workgroup's fused partial from its WAVES per-wave partials, in wave
+// order, widened to binary64 once.
+template <int IDT, int RACC, int WAVES>
+__device__ __forceinline__ double fused_block(const float* ws, const float* wc, const double* wd) {
+    if constexpr (IDT == DR_F64) {
+        double t = 0.0;
+        for (int i = 0; i < WAVES; ++i) t += wd[i];
+        return t;
+    } else if constexpr (RACC == DR_ACC_COMPENSATED) {
+        float ts = ws[0], tc = wc[0];
+        for (int i = 1; i < WAVES; ++i) pair_add(ts, tc, ws[i], wc[i]);
+        return pair_widen(ts, tc);
+    } else {
+        float ts = 0.0f;
+        for (int i = 0; i < WAVES; ++i) ts += ws[i];
+        return (double)ts;
     }
 }
 
@@ -341,7 +367,8 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
     using L = local_t<IDT>;
     using C = carry_t<IDT, C64>;
     __shared__ L s_wtot[WAVES];
-    __shared__ double s_red[WAVES];
+    __shared__ float s_rs[WAVES], s_rc[WAVES];
+    __shared__ double s_rd[WAVES];
 
     const int64_t stop = stop_of<REV>(a, si, T);
     const int w = threadIdx.x >> 6, l = lane_id();
@@ -351,8 +378,9 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
     vec<IDT> x[SLOTS], y[SLOTS];
     load_slots<IDT, SLOTS>(x, si.in0, si, u0, w, l, REV);
     if constexpr (ZIP) load_slots<IDT, SLOTS>(y, si.in1, si, u0, w, l, REV);
-    double rpart_thread = 0.0;
-    if constexpr (FUSED) rpart_thread = fused_partial<IDT, ROP, RACC, SLOTS>(x, y);
+    float rs = 0.0f, rc = 0.0f;
+    double rd = 0.0;
+    if constexpr (FUSED) fused_wave<IDT, ROP, RACC, SLOTS>(x, y, rs, rc, rd);
 
     L v[SLOTS][V];
     L base[SLOTS];
@@ -373,8 +401,11 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
     }
     if (threadIdx.x == 0) tagged_store(tw + kInclWord, tag, to_bits(excl + agg));
     if constexpr (FUSED) {
-        const double wr = wave_sum(rpart_thread);
-        if (l == 0) s_red[w] = wr;
+        if (l == 0) {
+            s_rs[w] = rs;
+            s_rc[w] = rc;
+            s_rd[w] = rd;
+        }
         __syncthreads();
     }
     // the initial value reaches the outputs only, never the published carries
@@ -382,8 +413,7 @@ __device__ __forceinline__ double scan_tile(const LaunchArgs& a, uint32_t tag, i
     tile_write<IDT, ODT, C64, SLOTS, REV>(v, base, eo, woff, si, u0, w, l, full, (a.flags & DR_SCAN_EXCLUSIVE) != 0);
     double part = 0.0;
     if constexpr (FUSED) {
-        if (threadIdx.x == 0)
-            for (int i = 0; i < WAVES; ++i) part += s_red[i];
+        if (threadIdx.x == 0) part = fused_block<IDT, RACC, WAVES>(s_rs, s_rc, s_rd);
     }
     return part;
 }
@@ -624,7 +654,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
     using L = local_t<IDT>;
     using C = carry_t<IDT, C64>;
     __shared__ L s_wtot[WAVES];
-    __shared__ double s_red[WAVES];
+    __shared__ float s_rs[WAVES], s_rc[WAVES];
+    __shared__ double s_rd[WAVES];
     const uint32_t tag = FUSED ? begin_launch(a.ws) : 0u;
     TileMap tm;
     tm.init(a);
@@ -654,16 +685,20 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
     const bool full = tile_full<V, SLOTS>(si, u0);
     vec<IDT, V> x[SLOTS], y[SLOTS];
     load_pair<ZIP, IDT, SLOTS, V>(x, y, si, u0, w, l, REV);
-    double rpart_thread = 0.0;
-    if constexpr (FUSED) rpart_thread = fused_partial<IDT, ROP, RACC, SLOTS>(x, y);
+    float fws = 0.0f, fwc = 0.0f;
+    double fwd = 0.0;
+    if constexpr (FUSED) fused_wave<IDT, ROP, RACC, SLOTS>(x, y, fws, fwc, fwd);
     const bool mn = (a.flags & kFlagMin) != 0;
     L v[SLOTS][V];
     L base[SLOTS];
     const L run = tile_values<IDT, OP, ZIP, SLOTS, REV, CMB, V>(x, y, (L)a.alpha, v, base, mn, si, u0, full);
     if (l == 0) s_wtot[w] = run;
     if constexpr (FUSED) {
-        const double wr = wave_sum(rpart_thread);
-        if (l == 0) s_red[w] = wr;
+        if (l == 0) {
+            s_rs[w] = fws;
+            s_rc[w] = fwc;
+            s_rd[w] = fwd;
+        }
     }
     __syncthreads();
     L woff = cmb_id<CMB, L>(mn);
@@ -675,16 +710,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(LaunchArgs a) {
     if constexpr (FUSED) {
         if (threadIdx.x >= 64) return;   // wave 0 publishes the partial and combines
         double part = 0.0;
-        if (l == 0)
-            for (int i = 0; i < WAVES; ++i) part += s_red[i];
+        if (l == 0) part = fused_block<IDT, RACC, WAVES>(s_rs, s_rc, s_rd);
         if (a.mode == DR_MODE_BATCH) combine_tile_batch<double>(a, tag, t, si, part);
         else combine_member<double>(a, tag, 0, 0, t, T, 0, part);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Single-pass form with specialised waves (the default for large scans of
-// tables that need no plan)
+// Single-pass form with specialised waves (on request: DR_TUNE_SPECIALIZED)
 // ---------------------------------------------------------------------------
 //
 // One workgroup per CU, all resident (cooperative launch); workgroup 0 is
@@ -733,7 +766,7 @@ __device__ __forceinline__ bool ws_wait(const int* p, int target, const LaunchAr
     Deadline dl(a.spin_ticks);
     while (lds_ld(p) < target) {
         if (dl.passed()) {
-            if (lane_id() == 0) flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
+            if (lane_id() == 0) flag_error(a, DR_DEVFLAG_TIMEOUT);
             return false;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -878,7 +911,7 @@ __device__ void ws_agent(const LaunchArgs& a, uint32_t tag, int64_t T) {
                 break;
             }
             if (s_to) {
-                if (tid == 0) flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
+                if (tid == 0) flag_error(a, DR_DEVFLAG_TIMEOUT);
                 return;
             }
             if (progress) {
@@ -931,7 +964,8 @@ __global__ __launch_bounds__(kWsThreads) void k_scan_ws(LaunchArgs a) {
     using C = carry_t<IDT, C64>;
     __shared__ vec<IDT> s_data[R][kBlock * SLOTS];
     __shared__ L s_wt[R][4];
-    __shared__ double s_red[R][4];
+    __shared__ float s_rs[R][4], s_rc[R][4];
+    __shared__ double s_rd[R][4];
     __shared__ int s_ready[R], s_done[R], s_cseq[R];
     __shared__ C s_carry[R];
 
@@ -985,21 +1019,24 @@ __global__ __launch_bounds__(kWsThreads) void k_scan_ws(LaunchArgs a) {
             const int slot = (int)(k % R);
             const int fill = (int)(k / R);
             L run = (L)0;
-            double part = 0.0;
+            float prs = 0.0f, prc = 0.0f;
+            double prd = 0.0;
             if (ok) {
                 const int64_t u0 = (phys(proc(k)) - si.first) * a.tile;
                 L v[SLOTS][V];
                 L base[SLOTS];
                 run = tile_values<IDT, OP, false, SLOTS, REV>(x, x, alpha, v, base, false, si, u0,
                                                               tile_full<V, SLOTS>(si, u0));
-                if constexpr (FUSED) part = wave_sum(fused_partial<IDT, ROP, RACC, SLOTS>(x, y));
+                if constexpr (FUSED) fused_wave<IDT, ROP, RACC, SLOTS>(x, y, prs, prc, prd);
             }
             if (!ws_wait(&s_done[slot], 5 * fill, a)) return false;
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) s_data[slot][(w * SLOTS + s) * 64 + l] = x[s];
             if (l == 0) {
                 s_wt[slot][w] = run;
-                s_red[slot][w] = part;
+                s_rs[slot][w] = prs;
+                s_rc[slot][w] = prc;
+                s_rd[slot][w] = prd;
                 lds_add(&s_ready[slot], 1);
             }
             return true;
@@ -1057,8 +1094,7 @@ __global__ __launch_bounds__(kWsThreads) void k_scan_ws(LaunchArgs a) {
             L tl = (L)0;
             for (int i = 0; i < 4; ++i) tl += s_wt[slot][i];
             double part = 0.0;
-            if (l == 0)
-                for (int i = 0; i < 4; ++i) part += s_red[slot][i];
+            if (l == 0) part = fused_block<IDT, RACC, 4>(s_rs[slot], s_rc[slot], s_rd[slot]);
             __builtin_amdgcn_s_waitcnt(0xc07f);
             if (l == 0) lds_add(&s_done[slot], 1);
             const int64_t r = proc(k);
@@ -1121,7 +1157,7 @@ __global__ __launch_bounds__(kWsThreads) void k_scan_ws(LaunchArgs a) {
             dl = Deadline(a.spin_ticks);
         } else {
             if (dl.passed()) {
-                if (l == 0) flag_error(a.ws, DR_DEVFLAG_TIMEOUT);
+                if (l == 0) flag_error(a, DR_DEVFLAG_TIMEOUT);
                 return;
             }
             for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(1);

@@ -27,6 +27,7 @@ Every generator takes an explicit seed (numpy PCG64); the default seeds are
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 
@@ -131,23 +132,44 @@ def ints_0_100(n: int, seed: int) -> np.ndarray:
 
 def mixture_f32(n: int, seed: int) -> np.ndarray:
     """50/50 mixture of |N(0,1)| and lognormal(0, 4), times an independent
-    random sign."""
-    g = rng(seed)
-    pick = g.random(n) < 0.5
-    mag = np.where(pick, np.abs(g.standard_normal(n)), np.exp(4.0 * g.standard_normal(n)))
-    sign = np.where(g.random(n) < 0.5, -1.0, 1.0)
-    return (sign * mag).astype(np.float32)
+    random sign: per element one binary32 standard normal z and two random
+    bits, b0 choosing |z| or exp(4 z), b1 the sign. Block b of 2^24
+    elements draws from its own PCG64 stream seeded by (seed, b), so the
+    blocks are generated on several threads and the values do not depend
+    on how many."""
+    out = np.empty(n, dtype=np.float32)
+    block = 1 << 24
+
+    def fill(o: int) -> None:
+        g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, o // block])))
+        m = min(block, n - o)
+        z = g.standard_normal(size=m, dtype=np.float32)
+        bits = g.integers(0, 4, size=m, dtype=np.uint8)
+        mag = np.where(bits & 1, np.abs(z), np.exp(np.float32(4.0) * z))
+        out[o:o + m] = np.where(bits & 2, -mag, mag)
+
+    starts = range(0, n, block)
+    if len(starts) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(len(starts), os.cpu_count() or 1, 16)) as ex:
+            list(ex.map(fill, starts))
+    else:
+        for o in starts:
+            fill(o)
+    return out
 
 
 def bf16_bits(x: np.ndarray) -> np.ndarray:
     """Round FP32 values to bfloat16 (round to nearest, ties to even) and
     return the 16-bit patterns as uint16. NaN stays a quiet NaN."""
-    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    lsb = (b >> np.uint64(16)) & np.uint64(1)
-    rounded = (b + np.uint64(0x7FFF) + lsb) >> np.uint64(16)
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32)
+    lsb = (b >> np.uint32(16)) & np.uint32(1)
+    # uint32 arithmetic wraps only for NaN patterns, which are set below
+    rounded = (b + np.uint32(0x7FFF) + lsb) >> np.uint32(16)
+    out = rounded.astype(np.uint16)
     nan = np.isnan(x)
-    out = (rounded & np.uint64(0xFFFF)).astype(np.uint16)
-    out[nan] = ((b[nan] >> np.uint64(16)) | np.uint64(0x40)).astype(np.uint16)
+    if nan.any():
+        out[nan] = ((b[nan] >> np.uint32(16)) | np.uint32(0x40)).astype(np.uint16)
     return out
 
 

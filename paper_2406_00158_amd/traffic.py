@@ -21,7 +21,7 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["dr_device.hpp", "dr_internal.hpp", "dr_combine.hpp", "k_elementwise.hip", "k_reduce.hip",
-                  "k_scan.hip", "k_plan.hip", "dr_api.cpp"]
+                  "k_scan.hip", "k_plan.hip", "dr_api.cpp", "dr_static.hip"]
 COPY_ELEMS = 1 << 28
 
 

@@ -106,11 +106,21 @@ def scan_fp32_bound(ref: np.ndarray, absprefix: np.ndarray, items: int = ITEMS, 
 
 
 def reduce_bound(absum: float, acc: str, items: int = ITEMS, in_bytes: int = 4, tiles: int = 1) -> float:
-    """|R - R_ref| bound of a reduction: binary32 inside the tile (plain:
-    recursive sum of `items` then a 256-wide binary32 tree; compensated:
-    TwoSum/TwoProduct pairs leave second-order terms), binary64 across."""
+    """|R - R_ref| bound of a reduction of `tiles` tiles of 256 * `items`
+    elements. binary32 / bfloat16 inputs accumulate in binary32 through the
+    workgroup: each thread runs serially over its elements (its tile's
+    `items`, or in the streaming form those of every tile its workgroup
+    takes: at most ceil(tiles / 256) tiles, the device running at least one
+    workgroup per CU), then a 64-lane tree and the 4 waves in order; plain:
+    recursive summation, (n + 10) u32 sum|v|; compensated: TwoSum/TwoProduct
+    pairs leave only second-order terms, 4 ((n + 10) u32)^2 sum|v| (Ogita,
+    Rump and Oishi's Sum2 / Dot2). The workgroup partials are widened and
+    combined in binary64 over a tree of depth 2 log2(tiles) + a few."""
+    per_thread = items * max(1, -(-tiles // 256))
+    b64 = (2 * np.log2(max(tiles, 2)) + 8) * U64 * absum
     if in_bytes == 8:
-        return (items + 8 + 2 * np.log2(max(tiles, 2)) + 4) * U64 * absum
+        return (per_thread + 10) * U64 * absum + b64
+    depth = per_thread + 10
     if acc == "plain":
-        return (items + 8 + 2) * U32 * absum + (2 * np.log2(max(tiles, 2)) + 4) * U64 * absum
-    return 4 * (items * U32) ** 2 * absum + (2 * np.log2(max(tiles, 2)) + 8) * U64 * absum
+        return depth * U32 * absum + b64
+    return 4 * (depth * U32) ** 2 * absum + b64

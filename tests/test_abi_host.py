@@ -30,6 +30,10 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(B.EXPORTS)
 
 
+def test_check_device_error_rejects_null_flags():
+    assert B.lib().dr_check_device_error(None, None) == B.DR_ERR_INVALID_ARG
+
+
 def test_version_and_status_strings():
     L = B.lib()
     assert L.dr_abi_version() == 1

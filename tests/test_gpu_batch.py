@@ -66,6 +66,14 @@ def test_graph_capture_and_replay():
     _run(tab, res, ws)                       # eager: plans and sizes the workspace
     torch.cuda.synchronize()
     ref_s, ref_r = s.clone(), res.clone()
+    # the eager result (and with it every replay, compared bit for bit below)
+    # against the oracle
+    want_s, absp = O.scan(I.split(xs, lengths), None, O.F32, O.IDENTITY, mode=O.BATCH, want_abs=True)
+    want_s, absp = np.concatenate(want_s), np.concatenate(absp)
+    assert np.all(np.abs(dev_to_np(ref_s).astype(np.float64) - want_s) <=
+                  scan_fp32_bound(want_s, absp, tiles=(1 << 22) // 4096 + 2000))
+    want_r, mag = O.reduce(I.split(xs, lengths), I.split(ys, lengths), O.F32, O.MUL, mode=O.BATCH)
+    assert np.all(np.abs(dev_to_np(ref_r) - want_r) <= reduce_bound(mag, "compensated", tiles=64))
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())

@@ -194,6 +194,18 @@ def test_batch_10000_ranges_forward_backward():
     wy = np.concatenate(O.reduce_grad(I.split(t["x"], L), I.split(t["y"], L), O.F32, O.MUL, dev_to_np(g), 1,
                                       mode=O.BATCH))
     assert np.array_equal(dev_to_np(gy), wy.astype(np.float32))
+    del wy, gy
+    # the scan's adjoint at full size: a reverse (suffix) scan of an upstream
+    # gradient per range, against the binary64 oracle
+    up_np = I.normal_f32(sum(L), 78)
+    up = torch.from_numpy(up_np).to(dev())
+    B.dr_inclusive_scan(B.segments([_pieces(up, L)], [_pieces(gx, L)], mode="batch"),
+                        B.make_view("identity", B.DR_F32), B.DR_F32, B.DR_SCAN_REVERSE)
+    ref, absp = O.scan(I.split(up_np, L), None, O.F32, O.IDENTITY, mode=O.BATCH, reverse=True, want_abs=True)
+    ref, absp = np.concatenate(ref), np.concatenate(absp)
+    err = np.abs(dev_to_np(gx).astype(np.float64) - ref)
+    print(f"batched reverse scan: max err / A_i {np.max(err / np.maximum(absp, 1e-300)):.3e}")
+    assert np.all(err <= scan_fp32_bound(ref, absp, tiles=(1 << 28) // 4096 + len(L)))
 
 
 def test_black_scholes_2_28_options_sampled():

@@ -332,6 +332,30 @@ def test_triad_is_two_roundings_like_numpy_float32():
     assert np.any(fused.view(np.uint32) != out.view(np.uint32))
 
 
+def test_binary64_for_each_is_numpy_float64_arithmetic():
+    """The binary64 branch: every op is numpy's float64 arithmetic with one
+    rounding per operation (axpy = fl(x + fl(alpha * y)), never fused),
+    bit for bit, over several segmentations and special values."""
+    rng = np.random.default_rng(61)
+    n = 4099
+    x = rng.standard_normal(n) * np.exp(rng.uniform(-30, 30, n))
+    y = rng.standard_normal(n) * np.exp(rng.uniform(-30, 30, n))
+    x[:6] = [0.0, -0.0, np.inf, -np.inf, np.nan, 5e-324]
+    y[:6] = [1.0, np.inf, -2.0, 0.0, 1.0, 3.0]
+    alpha = 0.1   # not a power of two: alpha * y rounds
+    with np.errstate(invalid="ignore", over="ignore"):
+        want = {O.IDENTITY: x.copy(), O.SQUARE: x * x, O.MUL: x * y, O.AXPY: x + alpha * y}
+    for L in ([n], [1, 0, 2048, 2050], I.lengths_dirichlet(n, 7, 1.0, 62)):
+        for op, w in want.items():
+            b = I.split(y, L) if O.ARITY[op] == 2 else None
+            got = np.concatenate(O.for_each(I.split(x, L), b, O.F64, op, O.F64, alpha=alpha))
+            assert got.dtype == np.float64
+            assert np.array_equal(got.view(np.uint64), w.view(np.uint64)), (op, L)
+    # and axpy is not the singly rounded (fused) result everywhere
+    fused = [float(Fraction(a) + Fraction(alpha) * Fraction(b)) for a, b in zip(x[6:400], y[6:400])]
+    assert np.any(np.array(fused) != want[O.AXPY][6:400])
+
+
 def test_bf16_decode_known_patterns():
     bits = np.array([0x3F80, 0xC000, 0x4049, 0x7F80, 0xFF80, 0x0001, 0x8000], dtype=np.uint16)
     out = O.for_each([bits], None, O.BF16, O.IDENTITY, O.F32)[0]
@@ -398,6 +422,39 @@ def test_gradients_match_central_differences():
                              mode=O.BATCH, alpha=2.5)
             fd = float(np.dot(g, (rp - rm) / (2 * h)))
             assert abs(fd - grad[i]) <= 1e-6 * (1 + abs(grad[i]))
+
+
+def test_constant_derivatives_are_exact_and_match_central_differences():
+    """d/dx of the identity view is 1 and d/dx0 of axpy is 1, so their
+    gradients are the upstream gradient of the element's range, exactly;
+    d/dx1 of axpy is alpha. Central differences of the binary64 reduce
+    agree (the maps are linear, so only rounding separates them)."""
+    rng = np.random.default_rng(44)
+    L = [1, 7, 0, 56]
+    n = sum(L)
+    x = rng.standard_normal(n)
+    y = rng.standard_normal(n)
+    g = rng.standard_normal(len(L))
+    per_elem = np.repeat(g, L)
+    for op, which, b, scale in ((O.IDENTITY, 0, None, 1.0), (O.AXPY, 0, I.split(y, L), 1.0),
+                                (O.AXPY, 1, I.split(y, L), 2.5)):
+        for mode in (O.BATCH, O.CONCAT):
+            gg = g if mode == O.BATCH else g[:1]
+            grad = np.concatenate(O.reduce_grad(I.split(x, L), b, O.F64, op, gg, which, mode=mode, alpha=2.5))
+            want = (per_elem if mode == O.BATCH else np.full(n, g[0])) * scale
+            assert np.array_equal(grad, want), (op, which, mode)
+    h = 1e-3
+    for op, which in ((O.IDENTITY, 0), (O.AXPY, 0)):
+        b = I.split(y, L) if O.ARITY[op] == 2 else None
+        grad = np.concatenate(O.reduce_grad(I.split(x, L), b, O.F64, op, g, which, mode=O.BATCH, alpha=2.5))
+        for i in range(n):
+            xp, xm = x.copy(), x.copy()
+            xp[i] += h
+            xm[i] -= h
+            rp, _ = O.reduce(I.split(xp, L), b, O.F64, op, mode=O.BATCH, alpha=2.5)
+            rm, _ = O.reduce(I.split(xm, L), b, O.F64, op, mode=O.BATCH, alpha=2.5)
+            fd = float(np.dot(g, (rp - rm) / (2 * h)))
+            assert abs(fd - grad[i]) <= 1e-9 * (1 + abs(grad[i]))
 
 
 def test_reverse_scan_is_the_adjoint_of_the_scan():
