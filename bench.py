@@ -2,29 +2,39 @@
 """Benchmark of the segmented for_each / transform_reduce / inclusive_scan
 path on one MI355X.
 
-Workload ("stream triad + dot", 2^28 binary32 elements, 8 equal segments,
-uniform[-1, 1), s = 3): one step is one pass of the whole hot path over it:
+One step is one pass of the whole hot path over the four full-size
+workloads (seeded synthetic inputs, resident in HBM before timing):
 
-  1. for_each      a = b + s*c                     (zip | transform | for_each)
-  2. reduce        R = dot(b, c), compensated       (zip | transform(mul) | reduce)
-  3. scan          S = inclusive_scan(a), binary64 carries across tiles/segments
-  4. batched       per segment: scan(b) and dot(b, c) fused in one launch
-  5. backward      dR/db = g*c, dR/dc = g*b (broadcast multiply), and the scan
-                   adjoint: reverse inclusive scan of an upstream gradient
+  triad      2^28 binary32, 8 equal segments: for_each a = b + 3c, and the
+             compensated dot(b, c)
+  scan       2^30 int32 U{0..100} in 16 Dirichlet(1) segments -> int64, and
+             -> int32 (wrapping); 2^28 binary32 N(0,1) in 16 Dirichlet(1)
+             segments with binary64 carries, and with binary32 carries
+  precision  2^29 values of the |N(0,1)| / lognormal(0,4) mixture, binary32
+             and bfloat16: sum of squares and dot, compensated and plain
+  batch      10,000 ragged binary32 ranges (2^28 in all): the fused per-range
+             scan + dot replayed from a hipGraph; backward: the dot's
+             adjoint (broadcast multiply) and the scan's (reverse scan)
 
-`value` is the whole step's algorithmic HBM bytes (each input read once, each
-output written once) divided by its time. `roofline` is for the kernel that
-takes the largest share of the step, timed with HIP events on its stream.
-`cpu_baseline` times the serial CPU oracle on a bounded sample of the same
-workload. Inputs are resident in HBM before timing starts.
+`value` is the step's algorithmic HBM bytes (each input read once, each
+output written once) divided by its time. `config.per_op` gives every
+operation's time, GB/s, fraction of the 8 TB/s peak and (from the CPU leg)
+its error against the binary64 oracle. `roofline` is for the longest-running
+operation that is one kernel launch, timed with HIP events on its stream.
+`cpu_baseline` times the oracle on the host: once serially (one thread) and
+once on every core, beside plain binary32 loops; its outputs are the
+references of the error figures.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py --configs     # every workload alone, median / p10 / p90
+    python bench.py --copy-only   # the copy kernel that calibrates the counters
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -35,9 +45,7 @@ from paper_2406_00158_amd.traffic import sources_hash  # noqa: E402 (no torch im
 
 METRIC = "effective HBM GB/s (% of peak) for fused reduce/scan; batched+compensated vs plain"
 HBM_PEAK_GBS = 8000.0
-N = 1 << 28
-SEGMENTS = 8
-SCALAR = 3.0
+U32 = 2.0 ** -24
 
 
 def load_traffic(kernel: str):
@@ -55,42 +63,367 @@ def load_traffic(kernel: str):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def cpu_baseline(reps: int = 3) -> dict:
-    """The serial oracle (plain C, one thread) on the same workload (all
-    2^28 elements, same segments), the same five steps, `reps` times."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+# ---------------------------------------------------------------------------
+# The step
+# ---------------------------------------------------------------------------
+
+class Op:
+    def __init__(self, name, nbytes, fn, kernel=None):
+        self.name, self.nbytes, self.fn = name, nbytes, fn
+        self.kernel = kernel   # the one kernel the call launches (besides a few-us prologue), or None
+
+
+def setup(dev):
+    """Inputs of the four workloads on the device, the tables, and the step's
+    operations. Returns (ops, host, out): `host` keeps the seeded inputs for
+    the oracle, `out` the device outputs the error figures compare."""
+    import numpy as np
+    import torch
+
+    from paper_2406_00158_amd import binding as B
+    from paper_2406_00158_amd import inputs as I
+
+    def to_dev(a):
+        if a.dtype == np.uint16:
+            return torch.from_numpy(a.view(np.int16)).to(dev).view(torch.bfloat16)
+        return torch.from_numpy(a).to(dev)
+
+    def pieces(t, lengths):
+        out, o = [], 0
+        for n in lengths:
+            out.append(t[o:o + n])
+            o += n
+        return out
+
+    host, out, ops = {}, {}, []
+    f32, v_id = B.DR_F32, B.make_view("identity", B.DR_F32)
+
+    # triad: 2^28 binary32, 8 equal segments
+    t = I.triad()
+    L2 = t["lengths"]
+    host["triad"] = t
+    b, c = to_dev(t["b"]), to_dev(t["c"])
+    a = torch.empty_like(b)
+    out["triad_a"] = a
+    t_tr = B.segments([pieces(b, L2), pieces(c, L2)], [pieces(a, L2)])
+    t_dot = B.segments([pieces(b, L2), pieces(c, L2)])
+    ws2 = B.Workspace(dev)
+    r_dot = torch.zeros(1, dtype=torch.float64, device=dev)
+    out["triad_dot"] = r_dot
+    n2 = sum(L2)
+    v_axpy, v_mul = B.make_view("axpy", f32, t["s"]), B.make_view("mul", f32)
+    ops.append(Op("triad: for_each a = b + 3c", 12 * n2,
+                  lambda: B.dr_for_each(t_tr, v_axpy, f32, workspace=ws2, host_check=False), "k_for_each"))
+    ops.append(Op("triad: dot(b, c) compensated", 8 * n2,
+                  lambda: B.dr_transform_reduce(t_dot, v_mul, B.DR_ACC_COMPENSATED, 0.0, r_dot, workspace=ws2,
+                                                host_check=False), "k_reduce_stream<1, 2, 1, 16>"))
+
+    # scan: 2^30 int32 (16 Dirichlet segments) and 2^28 binary32 (its own 16)
+    t = I.scan_int()
+    L3 = t["lengths"]
+    host["scan_int"] = t
+    k = to_dev(t["k"])
+    n3 = k.numel()
+    k64 = torch.empty(n3, dtype=torch.int64, device=dev)
+    k32 = torch.empty(n3, dtype=torch.int32, device=dev)
+    out["scan_i64"], out["scan_i32"] = k64, k32
+    t64 = B.segments([pieces(k, L3)], [pieces(k64, L3)])
+    t32 = B.segments([pieces(k, L3)], [pieces(k32, L3)])
+    ws3 = B.Workspace(dev)
+    v_i = B.make_view("identity", B.DR_I32)
+    ops.append(Op("scan: int32 2^30 -> int64", 12 * n3,
+                  lambda: B.dr_inclusive_scan(t64, v_i, B.DR_I64, workspace=ws3, host_check=False)))
+    ops.append(Op("scan: int32 2^30 -> int32 (wrap)", 8 * n3,
+                  lambda: B.dr_inclusive_scan(t32, v_i, B.DR_I32, workspace=ws3, host_check=False)))
+    t = I.scan_fp()
+    L3f = t["lengths"]
+    host["scan_fp"] = t
+    xf = to_dev(t["x"])
+    n3f = xf.numel()
+    yf64, yf32 = torch.empty_like(xf), torch.empty_like(xf)
+    out["scan_f_c64"], out["scan_f_c32"] = yf64, yf32
+    tf64 = B.segments([pieces(xf, L3f)], [pieces(yf64, L3f)])
+    tf32 = B.segments([pieces(xf, L3f)], [pieces(yf32, L3f)])
+    ops.append(Op("scan: f32 2^28, binary64 carries", 8 * n3f,
+                  lambda: B.dr_inclusive_scan(tf64, v_id, f32, 0, workspace=ws3, host_check=False)))
+    ops.append(Op("scan: f32 2^28, binary32 carries", 8 * n3f,
+                  lambda: B.dr_inclusive_scan(tf32, v_id, f32, B.DR_SCAN_CARRY_F32, workspace=ws3,
+                                              host_check=False)))
+
+    # precision: 2^29 mixture, binary32 and bfloat16, 8 equal segments
+    t = I.precision()
+    L4 = t["lengths"]
+    host["precision"] = t
+    n4 = sum(L4)
+    ws4 = B.Workspace(dev)
+    for dt, xs, ys, eb in (("f32", t["x"], t["y"], 4), ("bf16", t["x_bf16"], t["y_bf16"], 2)):
+        xd, yd = to_dev(xs), to_dev(ys)
+        bdt = B.DR_F32 if dt == "f32" else B.DR_BF16
+        items = 16 if dt == "f32" else 32
+        t1, tz = B.segments([pieces(xd, L4)]), B.segments([pieces(xd, L4), pieces(yd, L4)])
+        for acc in ("compensated", "plain"):
+            r1 = torch.zeros(1, dtype=torch.float64, device=dev)
+            r2 = torch.zeros(1, dtype=torch.float64, device=dev)
+            out[f"prec_{dt}_sumsq_{acc}"], out[f"prec_{dt}_dot_{acc}"] = r1, r2
+            ac = B.ACCS[acc]
+            kn = lambda arity: f"k_reduce_stream<{bdt}, {arity}, {ac}, {items}>"
+            ops.append(Op(f"precision: {dt} sum of squares, {acc}", eb * n4,
+                          (lambda t1=t1, v=B.make_view("square", bdt), ac=ac, r1=r1:
+                           B.dr_transform_reduce(t1, v, ac, 0.0, r1, workspace=ws4, host_check=False)),
+                          kn(1).replace(", 1, ", ", 1, ", 1)))
+            ops.append(Op(f"precision: {dt} dot, {acc}", 2 * eb * n4,
+                          (lambda tz=tz, v=B.make_view("mul", bdt), ac=ac, r2=r2:
+                           B.dr_transform_reduce(tz, v, ac, 0.0, r2, workspace=ws4, host_check=False)),
+                          kn(2)))
+    # the reduce kernels' template arguments: <in dtype, op, acc, items>
+    for o in ops:
+        if o.kernel and o.kernel.startswith("k_reduce_stream<") and "sum of squares" in o.name:
+            parts = o.kernel[len("k_reduce_stream<"):-1].split(", ")
+            o.kernel = f"k_reduce_stream<{parts[0]}, {B.DR_OP_SQUARE}, {parts[2]}, {parts[3]}>"
+        elif o.kernel and o.kernel.startswith("k_reduce_stream<") and "dot" in o.name and "precision" in o.name:
+            parts = o.kernel[len("k_reduce_stream<"):-1].split(", ")
+            o.kernel = f"k_reduce_stream<{parts[0]}, {B.DR_OP_MUL}, {parts[2]}, {parts[3]}>"
+
+    # batch: 10,000 ragged ranges, fused scan + dot from a graph, backward
+    t = I.batch()
+    L5 = t["lengths"]
+    host["batch"] = t
+    n5 = sum(L5)
+    x5, y5 = to_dev(t["x"]), to_dev(t["y"])
+    s5 = torch.empty_like(x5)
+    r5 = torch.zeros(len(L5), dtype=torch.float64, device=dev)
+    out["batch_s"], out["batch_r"] = s5, r5
+    ws5, ws5b, ws5r = B.Workspace(dev), B.Workspace(dev), B.Workspace(dev)
+    t5 = B.segments([pieces(x5, L5), pieces(y5, L5)], [pieces(s5, L5)], mode="batch")
+    fused = lambda: B.dr_scan_reduce(t5, v_id, v_mul, B.DR_ACC_COMPENSATED, 0.0, r5, workspace=ws5,
+                                     host_check=False)
+    fused()                                 # eager: plans and sizes the workspace
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        fused()
+    torch.cuda.current_stream(dev).wait_stream(side)
+    with torch.cuda.graph(graph):
+        fused()
+    ops.append(Op("batch: fused scan + dot per range (hipGraph replay)", 12 * n5, graph.replay))
+    g5_np = I.normal_f32(len(L5), 1105).astype(np.float64)
+    up5_np = I.normal_f32(n5, 1106)
+    host["batch_g"], host["batch_up"] = g5_np, up5_np
+    g5, up5 = torch.from_numpy(g5_np).to(dev), to_dev(up5_np)
+    gx5, gy5, gs5 = torch.empty_like(x5), torch.empty_like(y5), torch.empty_like(x5)
+    out["batch_gx"], out["batch_gy"], out["batch_gs"] = gx5, gy5, gs5
+    tbm = B.segments([pieces(x5, L5), pieces(y5, L5)], [pieces(gx5, L5), pieces(gy5, L5)], mode="batch")
+    trs = B.segments([pieces(up5, L5)], [pieces(gs5, L5)], mode="batch")
+    ops.append(Op("batch: backward, dot adjoint (broadcast multiply)", 16 * n5,
+                  lambda: B.dr_broadcast_mul(tbm, v_mul, g5, 2, workspace=ws5b, host_check=False),
+                  "k_broadcast_mul<1, 2, 16, 2>"))
+    ops.append(Op("batch: backward, scan adjoint (reverse scan)", 8 * n5,
+                  lambda: B.dr_inclusive_scan(trs, v_id, f32, B.DR_SCAN_REVERSE, workspace=ws5r,
+                                              host_check=False)))
+    out["workspaces"] = [ws2, ws3, ws4, ws5, ws5b, ws5r]
+    out["graph"] = graph
+    return ops, host, out
+
+
+# ---------------------------------------------------------------------------
+# CPU leg: the oracle (references of the error figures), its twin on every
+# core, and plain binary32 loops
+# ---------------------------------------------------------------------------
+
+def cpu_leg(host, out, reps_parallel: int = 1) -> tuple[dict, dict]:
+    """Returns (errors by op name, cpu_baseline)."""
     import numpy as np
 
     import oracle as O
+    import oracle.parallel as OP
+    import oracle.plain as PL
     from paper_2406_00158_amd import inputs as I
 
-    t = I.triad(n=N, segments=SEGMENTS)
+    def d2h(t, lo=None, hi=None):
+        v = t if lo is None else t[lo:hi]
+        return v.cpu().numpy()
+
+    err, work = {}, 0
+    t_serial = 0.0
+
+    def timed(fn):
+        nonlocal t_serial
+        t0 = time.perf_counter()
+        r = fn()
+        t_serial += time.perf_counter() - t0
+        return r
+
+    def scan_metrics(got, ref, absp):
+        e = np.abs(got.astype(np.float64) - ref)
+        return {"max_abs_err": float(e.max()), "max_err_over_abs_prefix": float(np.max(e / np.maximum(absp, 1e-300))),
+                "frac_equal_fl32_ref": float(np.mean(got == ref.astype(np.float32)))}
+
+    def rel(gotv, want, mag):
+        return {"rel_err": abs(gotv - want) / abs(want), "cond": mag / abs(want)}
+
+    # triad
+    t = host["triad"]
     L = t["lengths"]
     b, c = I.split(t["b"], L), I.split(t["c"], L)
-    g = np.ones(1)
+    want = np.concatenate(timed(lambda: O.for_each(b, c, O.F32, O.AXPY, O.F32, alpha=t["s"])))
+    got = d2h(out["triad_a"])
+    err["triad: for_each a = b + 3c"] = {"bit_exact": bool(np.array_equal(got.view(np.uint32), want.view(np.uint32))),
+                                         "mismatches": int(np.sum(got.view(np.uint32) != want.view(np.uint32)))}
+    w, m = timed(lambda: O.reduce(b, c, O.F32, O.MUL))
+    err["triad: dot(b, c) compensated"] = rel(out["triad_dot"].item(), w[0], m[0])
+    work += 20 * sum(L)
+    del want, got
+
+    # scans
+    t = host["scan_int"]
+    L = t["lengths"]
+    k = I.split(t["k"], L)
+    for odt, key, name in ((O.I64, "scan_i64", "scan: int32 2^30 -> int64"),
+                           (O.I32, "scan_i32", "scan: int32 2^30 -> int32 (wrap)")):
+        want = np.concatenate(timed(lambda: O.scan(k, None, O.I32, O.IDENTITY, out_dtype=odt)))
+        mism, step = 0, 1 << 26
+        for lo in range(0, want.shape[0], step):
+            hi = min(lo + step, want.shape[0])
+            mism += int(np.sum(d2h(out[key], lo, hi) != want[lo:hi]))
+        err[name] = {"bit_exact": mism == 0, "mismatches": mism}
+        work += (12 if odt == O.I64 else 8) * want.shape[0]
+        del want
+    t = host["scan_fp"]
+    L = t["lengths"]
+    ref, absp = timed(lambda: O.scan(I.split(t["x"], L), None, O.F32, O.IDENTITY, want_abs=True))
+    ref, absp = np.concatenate(ref), np.concatenate(absp)
+    err["scan: f32 2^28, binary64 carries"] = scan_metrics(d2h(out["scan_f_c64"]), ref, absp)
+    err["scan: f32 2^28, binary32 carries"] = scan_metrics(d2h(out["scan_f_c32"]), ref, absp)
+    work += 8 * ref.shape[0]
+    del ref, absp
+
+    # precision
+    t = host["precision"]
+    L = t["lengths"]
+    for dt, xs, ys, odt in (("f32", t["x"], t["y"], O.F32), ("bf16", t["x_bf16"], t["y_bf16"], O.BF16)):
+        xl, yl = I.split(xs, L), I.split(ys, L)
+        wsq, msq = timed(lambda: O.reduce(xl, None, odt, O.SQUARE))
+        wd, md = timed(lambda: O.reduce(xl, yl, odt, O.MUL))
+        for acc in ("compensated", "plain"):
+            err[f"precision: {dt} sum of squares, {acc}"] = rel(out[f"prec_{dt}_sumsq_{acc}"].item(), wsq[0], msq[0])
+            err[f"precision: {dt} dot, {acc}"] = rel(out[f"prec_{dt}_dot_{acc}"].item(), wd[0], md[0])
+        work += 3 * xs.nbytes
+
+    # batch
+    t = host["batch"]
+    L = t["lengths"]
+    xl, yl = I.split(t["x"], L), I.split(t["y"], L)
+    ref, absp = timed(lambda: O.scan(xl, None, O.F32, O.IDENTITY, mode=O.BATCH, want_abs=True))
+    ref, absp = np.concatenate(ref), np.concatenate(absp)
+    e_scan = scan_metrics(d2h(out["batch_s"]), ref, absp)
+    del ref, absp
+    w, m = timed(lambda: O.reduce(xl, yl, O.F32, O.MUL, mode=O.BATCH))
+    got = d2h(out["batch_r"])
+    r_err = np.abs(got - w) / np.maximum(np.abs(w), 1e-300)
+    e_scan.update({"dot_max_rel_err": float(r_err.max()), "dot_median_rel_err": float(np.median(r_err)),
+                   "dot_max_cond": float(np.max(m / np.maximum(np.abs(w), 1e-300)))})
+    err["batch: fused scan + dot per range (hipGraph replay)"] = e_scan
+    g = host["batch_g"]
+    mism = 0
+    for which, key in ((0, "batch_gx"), (1, "batch_gy")):
+        wg = np.concatenate(timed(lambda: O.reduce_grad(xl, yl, O.F32, O.MUL, g, which, mode=O.BATCH)))
+        mism += int(np.sum(d2h(out[key]).view(np.uint32) != wg.astype(np.float32).view(np.uint32)))
+        del wg
+    err["batch: backward, dot adjoint (broadcast multiply)"] = {"bit_exact": mism == 0, "mismatches": mism}
+    up = host["batch_up"]
+    ref, absp = timed(lambda: O.scan(I.split(up, L), None, O.F32, O.IDENTITY, mode=O.BATCH, reverse=True,
+                                     want_abs=True))
+    ref, absp = np.concatenate(ref), np.concatenate(absp)
+    err["batch: backward, scan adjoint (reverse scan)"] = scan_metrics(d2h(out["batch_gs"]), ref, absp)
+    del ref, absp
+    work += 36 * sum(L)
+
+    # the oracle on every core (the same operations), and plain loops
+    nthreads = OP.threads()
     t0 = time.perf_counter()
-    for _ in range(reps):
-        a = O.for_each(b, c, O.F32, O.AXPY, O.F32, alpha=SCALAR)
-        O.reduce(b, c, O.F32, O.MUL)
-        O.scan(a, None, O.F32, O.IDENTITY)
-        O.scan(b, None, O.F32, O.IDENTITY, mode=O.BATCH)
-        O.reduce(b, c, O.F32, O.MUL, mode=O.BATCH)
-        O.reduce_grad(b, c, O.F32, O.MUL, g, 0)
-        O.reduce_grad(b, c, O.F32, O.MUL, g, 1)
-        O.scan(a, None, O.F32, O.IDENTITY, reverse=True)
-        del a
-    dt = time.perf_counter() - t0
-    return {"value": round(reps * step_bytes(N) / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"the whole workload (2^28 elements, {SEGMENTS} segments), the same five steps "
-                      f"{reps} times, serial C oracle (gcc -O2, binary64/int64 arithmetic), one thread, "
-                      f"{dt:.2f} s"}
+    t = host["triad"]
+    OP.for_each(t["b"], t["c"], O.F32, O.AXPY, O.F32, alpha=t["s"])
+    OP.reduce(t["b"], t["c"], O.F32, O.MUL)
+    OP.scan(host["scan_int"]["k"], O.I32, O.I64)
+    OP.scan(host["scan_int"]["k"], O.I32, O.I32)
+    OP.scan(host["scan_fp"]["x"], O.F32)
+    t = host["precision"]
+    for xs, ys, odt in ((t["x"], t["y"], O.F32), (t["x_bf16"], t["y_bf16"], O.BF16)):
+        OP.reduce(xs, None, odt, O.SQUARE)
+        OP.reduce(xs, ys, odt, O.MUL)
+    t = host["batch"]
+    L = t["lengths"]
+    OP.scan_batch(t["x"], L)
+    OP.reduce_batch(t["x"], t["y"], L)
+    OP.reduce_grad_batch(t["x"], t["y"], L, host["batch_g"], 0)
+    OP.reduce_grad_batch(t["x"], t["y"], L, host["batch_g"], 1)
+    OP.scan_batch(host["batch_up"], L, reverse=True)
+    t_par = time.perf_counter() - t0
+
+    Pl = PL.lib()
+    p = PL.ptr
+    t0 = time.perf_counter()
+    t = host["triad"]
+    a = np.empty_like(t["b"])
+    Pl.plain_triad(a.shape[0], p(t["b"]), p(t["c"]), p(a), t["s"])
+    Pl.plain_dot_f32(a.shape[0], p(t["b"]), p(t["c"]))
+    del a
+    k = host["scan_int"]["k"]
+    y64 = np.empty(k.shape[0], dtype=np.int64)
+    Pl.plain_scan_i32_i64(k.shape[0], p(k), p(y64))
+    del y64
+    y32 = np.empty_like(k)
+    Pl.plain_scan_i32_i32(k.shape[0], p(k), p(y32))
+    del y32
+    x = host["scan_fp"]["x"]
+    yf = np.empty_like(x)
+    Pl.plain_scan_f32(x.shape[0], p(x), p(yf))
+    del yf
+    t = host["precision"]
+    n4 = t["x"].shape[0]
+    Pl.plain_sumsq_f32(n4, p(t["x"]))
+    Pl.plain_dot_f32(n4, p(t["x"]), p(t["y"]))
+    Pl.plain_sumsq_bf16(n4, p(t["x_bf16"]))
+    Pl.plain_dot_bf16(n4, p(t["x_bf16"]), p(t["y_bf16"]))
+    t = host["batch"]
+    lens = np.asarray(t["lengths"], dtype=np.int64)
+    s5, r5 = np.empty_like(t["x"]), np.empty(lens.shape[0])
+    Pl.plain_scan_f32_batch(lens.shape[0], p(lens), p(t["x"]), p(s5), 0)
+    Pl.plain_dot_f32_batch(lens.shape[0], p(lens), p(t["x"]), p(t["y"]), p(r5))
+    gx, gy = np.empty_like(t["x"]), np.empty_like(t["x"])
+    Pl.plain_bcast_mul_batch(lens.shape[0], p(lens), p(t["x"]), p(t["y"]), p(host["batch_g"]), p(gx), p(gy))
+    Pl.plain_scan_f32_batch(lens.shape[0], p(lens), p(host["batch_up"]), p(s5), 1)
+    t_plain = time.perf_counter() - t0
+    del s5, gx, gy
+
+    gbs = lambda s: round(work / s / 1e9, 3)
+    base = {"value": gbs(t_par), "unit": "GB/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"the whole step once (every operation of the four workloads at full size: {work / 1e9:.1f} GB "
+                      f"of algorithmic bytes, with the C4 plain/compensated pairs sharing one reference each), "
+                      f"the binary64 / int64 oracle (gcc -O2) on all {nthreads} host threads: {t_par:.2f} s",
+            "cpu_model": cpu_model(),
+            "serial": {"value": gbs(t_serial), "cores": 1, "seconds": round(t_serial, 2),
+                       "what": "the same oracle calls on one thread (they produced the error references)"},
+            "plain_f32_loop": {"value": gbs(t_plain), "cores": 1, "seconds": round(t_plain, 2),
+                               "what": "plain serial binary32 / int64 loops over the same operations (no "
+                                       "binary64, no compensation): the cost of the arithmetic alone"}}
+    return err, base
 
 
-BYTES_PER_ELEM = {"for_each": 12, "reduce": 8, "scan": 8, "batched": 12, "backward_mul": 16, "backward_scan": 8}
-
-
-def step_bytes(n: int) -> int:
-    return n * sum(BYTES_PER_ELEM.values())
-
+# ---------------------------------------------------------------------------
 
 def configs_report(reps: int) -> int:
     """Every workload of the hot path at its full size, timed alone: the
@@ -149,14 +482,25 @@ def configs_report(reps: int) -> int:
         return gbs
 
     # copy reference: for_each identity, 2^28 binary32 (1 GiB each way)
+    N = 1 << 28
     src = torch.rand(N, device=dev)
     dst = torch.empty_like(src)
     tcp = B.segments([[src]], [[dst]])
     copy_gbs[0] = report("copy", "for_each identity 2^28 f32", 8 * N,
-                         lambda: B.dr_for_each(tcp, B.make_view("identity", B.DR_F32), B.DR_F32, host_check=False))
-    del src, dst, tcp
+                         lambda: B.dr_for_each(tcp, B.make_view("identity", B.DR_F32), B.DR_F32, workspace=ws,
+                                               host_check=False))
+    # two reads and two writes through the library (the broadcast multiply's
+    # access pattern, with the identity view: gx = g * 1... written as a zip
+    # of two inputs and two outputs): the ceiling of a 2-in-2-out stream
+    src2 = torch.rand(N, device=dev)
+    dst2 = torch.empty_like(src)
+    t22 = B.segments([[src], [src2]], [[dst], [dst2]])
+    g1 = torch.ones(1, dtype=torch.float64, device=dev)
+    report("copy", "2 reads + 2 writes: broadcast multiply (mul view, g = 1) 2^28 f32", 16 * N,
+           lambda: B.dr_broadcast_mul(t22, B.make_view("mul", B.DR_F32), g1, 2, workspace=ws, host_check=False))
+    del src, dst, tcp, src2, dst2, t22
 
-    # C1 tiny: 2^20, 4 unequal segments, separate allocations and one carved buffer
+    # tiny: 2^20, 4 unequal segments, separate allocations and one carved buffer
     t = I.tiny()
     L = t["lengths"]
     n = sum(L)
@@ -185,11 +529,12 @@ def configs_report(reps: int) -> int:
     L = t["lengths"]
     b, c = to_dev(t["b"]), to_dev(t["c"])
     a = torch.empty_like(b)
+    s = t["s"]
     del t
     res = torch.zeros(1, dtype=torch.float64, device=dev)
     ttr, tdot = B.segments([pieces(b, L), pieces(c, L)], [pieces(a, L)]), B.segments([pieces(b, L), pieces(c, L)])
     report("C2 triad", "for_each a = b + 3c", 12 * N, lambda: B.dr_for_each(
-        ttr, B.make_view("axpy", B.DR_F32, SCALAR), B.DR_F32, host_check=False))
+        ttr, B.make_view("axpy", B.DR_F32, s), B.DR_F32, workspace=ws, host_check=False))
     for acc in ("compensated", "plain"):
         report("C2 triad", f"dot {acc}", 8 * N, lambda: B.dr_transform_reduce(
             tdot, B.make_view("mul", B.DR_F32), B.ACCS[acc], 0.0, res, workspace=ws, host_check=False))
@@ -218,8 +563,6 @@ def configs_report(reps: int) -> int:
     for fl, nm in ((0, "binary64 carries"), (B.DR_SCAN_CARRY_F32, "binary32 carries")):
         report("C3 scan", f"f32 2^28, {nm}", 8 * x.numel(), lambda: B.dr_inclusive_scan(
             tab, B.make_view("identity", B.DR_F32), B.DR_F32, fl, workspace=ws, host_check=False))
-    # the generic operators on the same data (section 4.3): exclusive sum with
-    # an initial value, running max, and max / min reductions
     vid = B.make_view("identity", B.DR_F32)
     report("C3 scan", "f32 2^28, exclusive sum with init", 8 * x.numel(), lambda: B.dr_scan(
         tab, vid, B.DR_F32, B.DR_COMBINE_SUM, B.DR_SCAN_EXCLUSIVE, 1.5, workspace=ws, host_check=False))
@@ -275,7 +618,6 @@ def configs_report(reps: int) -> int:
     with torch.cuda.graph(g):
         fused()
     report("C5 batch", "fused scan + dot, hipGraph replay", 12 * n5, g.replay)
-    # one workspace per table: a workspace holds the plan of one large table
     ws_s, ws_d, ws_b, ws_r = (B.Workspace(dev) for _ in range(4))
     report("C5 batch", "unfused: scan, then dot (two calls)", 16 * n5, lambda: (
         B.dr_inclusive_scan(tsc, vid, B.DR_F32, workspace=ws_s, host_check=False),
@@ -288,7 +630,6 @@ def configs_report(reps: int) -> int:
         tbm, vmul, gg, 2, workspace=ws_b, host_check=False))
     report("C5 batch", "backward: scan adjoint (reverse scan)", 8 * n5, lambda: B.dr_inclusive_scan(
         trs, vid, B.DR_F32, B.DR_SCAN_REVERSE, workspace=ws_r, host_check=False))
-    # one call per range, for the launch-count contrast (the batched call is one)
     per = [(B.segments([[xs], [ys]], [[ss]]), r5[i:i + 1]) for i, (xs, ys, ss) in
            enumerate(zip(pieces(x, L), pieces(y, L), pieces(s5, L)))]
     ws1 = B.Workspace(dev)
@@ -306,10 +647,10 @@ def configs_report(reps: int) -> int:
     call, put = torch.empty_like(ins[0]), torch.empty_like(ins[0])
     tbs = B.segments([pieces(a, L) for a in ins], [pieces(call, L), pieces(put, L)])
     report("Black-Scholes", "2^28 options: call and put", 24 * sum(L), lambda: B.dr_for_each(
-        tbs, B.make_view("black_scholes", B.DR_F32, t["r"]), B.DR_F32, host_check=False))
+        tbs, B.make_view("black_scholes", B.DR_F32, t["r"]), B.DR_F32, workspace=ws, host_check=False))
     del t, ins, call, put, tbs
 
-    flags = 0
+    flags = B.dr_check_device_error(dev)
     for w_ in (ws, ws5, ws1, ws_s, ws_d, ws_b, ws_r):
         flags |= w_.device_status()
     print(json.dumps({"device_fault_flags": flags}), flush=True)
@@ -321,16 +662,16 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU leg (oracle baseline and error figures)")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only a plain copy (for_each identity, 2^28 f32) K times: the known-size "
                          "kernel that calibrates the HBM byte counters")
     ap.add_argument("--configs", action="store_true",
-                    help="time every workload (tiny, triad, scans, precision, batch) alone at full size and "
-                         "print one JSON line per case instead of the step line")
+                    help="time every workload alone at full size and print one JSON line per case instead "
+                         "of the step line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
+        print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md describes how the "
               "path would shard); run with --gpus 1", file=sys.stderr)
         return 2
 
@@ -343,120 +684,73 @@ def main() -> int:
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(1002)
-    b = torch.rand(N, device=dev, generator=gen) * 2 - 1
-    c = torch.rand(N, device=dev, generator=gen) * 2 - 1
-    a = torch.empty(N, device=dev)
-    s = torch.empty(N, device=dev)
-    sb = torch.empty(N, device=dev)
-    gb = torch.empty(N, device=dev)
-    gc = torch.empty(N, device=dev)
-    gs = torch.empty(N, device=dev)
-    up = torch.ones(N, device=dev)          # upstream gradient of S
-
-    def seg(t):
-        k = N // SEGMENTS
-        return [t[i * k:(i + 1) * k] for i in range(SEGMENTS)]
 
     if args.copy_only:
-        t_copy = B.segments([seg(b)], [seg(a)])
+        N = 1 << 28
+        b = torch.rand(N, device=dev)
+        a = torch.empty(N, device=dev)
+        t_copy = B.segments([[b]], [[a]])
         v_copy = B.make_view("identity", B.DR_F32)
+        ws = B.Workspace(dev)
         for _ in range(args.warmup + args.steps):
-            B.dr_for_each(t_copy, v_copy, B.DR_F32, host_check=False)
+            B.dr_for_each(t_copy, v_copy, B.DR_F32, workspace=ws, host_check=False)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": 8 * N, "launches": args.warmup + args.steps}), flush=True)
         return 0
 
-    t_triad = B.segments([seg(b), seg(c)], [seg(a)])
-    t_dot = B.segments([seg(b), seg(c)])
-    t_scan = B.segments([seg(a)], [seg(s)])
-    t_batch = B.segments([seg(b), seg(c)], [seg(sb)], mode="batch")
-    t_grad = B.segments([seg(b), seg(c)], [seg(gb), seg(gc)])
-    t_rscan = B.segments([seg(up)], [seg(gs)])
-    ws = B.Workspace(dev)
-    ws_b = B.Workspace(dev)
-    R = torch.zeros(1, dtype=torch.float64, device=dev)
-    Rp = torch.zeros(1, dtype=torch.float64, device=dev)
-    Rb = torch.zeros(SEGMENTS, dtype=torch.float64, device=dev)
-    g = torch.ones(1, dtype=torch.float64, device=dev)
-    v_axpy = B.make_view("axpy", B.DR_F32, SCALAR)
-    v_mul = B.make_view("mul", B.DR_F32)
-    v_id = B.make_view("identity", B.DR_F32)
-
-    ops = {
-        "for_each": lambda: B.dr_for_each(t_triad, v_axpy, B.DR_F32, host_check=False),
-        "reduce": lambda: B.dr_transform_reduce(t_dot, v_mul, B.DR_ACC_COMPENSATED, 0.0, R, workspace=ws,
-                                                host_check=False),
-        "scan": lambda: B.dr_inclusive_scan(t_scan, v_id, B.DR_F32, 0, workspace=ws, host_check=False),
-        "batched": lambda: B.dr_scan_reduce(t_batch, v_id, v_mul, B.DR_ACC_COMPENSATED, 0.0, Rb, 0,
-                                            workspace=ws_b, host_check=False),
-        "backward_mul": lambda: B.dr_broadcast_mul(t_grad, v_mul, g, 2, host_check=False),
-        "backward_scan": lambda: B.dr_inclusive_scan(t_rscan, v_id, B.DR_F32, B.DR_SCAN_REVERSE, workspace=ws,
-                                                     host_check=False),
-    }
-
-    def step():
-        for fn in ops.values():
-            fn()
-
+    t_setup = time.perf_counter()
+    print("[bench] generating the seeded inputs of the four workloads", file=sys.stderr, flush=True)
+    ops, host, out = setup(dev)
+    t_setup = time.perf_counter() - t_setup
+    print(f"[bench] setup {t_setup:.1f} s; {len(ops)} operations per step", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream(dev)
+    step_bytes = sum(o.nbytes for o in ops)
+
     for _ in range(args.warmup):
-        step()
+        for o in ops:
+            o.fn()
     torch.cuda.synchronize()
 
-    # timed region: K whole steps, with per-kernel HIP events on the launch stream
-    ev = {k: [] for k in ops}
+    # timed region: K whole steps, with per-operation HIP events on the launch stream
+    ev = [[] for _ in ops]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
     for _ in range(args.steps):
-        for k, fn in ops.items():
+        for i, o in enumerate(ops):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            fn()
+            o.fn()
             e1.record(stream)
-            ev[k].append((e0, e1))
+            ev[i].append((e0, e1))
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    total_ms = start.elapsed_time(stop)
-    ms_per_step = total_ms / args.steps
-    per_op_ms = {k: sum(e0.elapsed_time(e1) for e0, e1 in v) / len(v) for k, v in ev.items()}
-    value = step_bytes(N) / (ms_per_step * 1e-3) / 1e9
+    ms_per_step = start.elapsed_time(stop) / args.steps
+    op_ms = [sum(e0.elapsed_time(e1) for e0, e1 in v) / len(v) for v in ev]
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    flags = B.dr_check_device_error(dev)
+    for w_ in out["workspaces"]:
+        flags |= w_.device_status()
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms per step", file=sys.stderr, flush=True)
 
-    # plain binary32 dot for the accuracy / cost contrast (outside the step)
-    for _ in range(3):
-        B.dr_transform_reduce(t_dot, v_mul, B.DR_ACC_PLAIN, 0.0, Rp, workspace=ws, host_check=False)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        B.dr_transform_reduce(t_dot, v_mul, B.DR_ACC_PLAIN, 0.0, Rp, workspace=ws, host_check=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = e0.elapsed_time(e1) / 10
-    flags = ws.device_status() | ws_b.device_status()
+    per_op = {}
+    for o, ms in zip(ops, op_ms):
+        gbs = o.nbytes / (ms * 1e-3) / 1e9
+        per_op[o.name] = {"ms": round(ms, 4), "bytes": o.nbytes, "GB/s": round(gbs, 1),
+                          "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
-    # roofline: the longest-running single kernel of the step. The ops
-    # below are one main kernel launch each (the reduce adds a 2-5 us
-    # counter-zeroing prologue), so HIP events around the op time that
-    # kernel; the scans are several passes in one call and are reported per
-    # op (per_op) and per kernel in the committed kernel-trace profile.
-    single = {"for_each": "k_for_each", "reduce": "k_reduce_stream", "backward_mul": "k_broadcast_mul"}
-    dom = max(single, key=lambda k: per_op_ms[k])
-    kernel_name = single[dom]
-    achieved = BYTES_PER_ELEM[dom] * N / (per_op_ms[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": kernel_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kernel_name),
-                "algorithmic_bytes_per_launch": BYTES_PER_ELEM[dom] * N}
-
-    per_op = {k: {"ms": round(v, 4), "GB/s": round(BYTES_PER_ELEM[k] * N / (v * 1e-3) / 1e9, 1),
-                  "frac_of_peak": round(BYTES_PER_ELEM[k] * N / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-              for k, v in per_op_ms.items()}
-    per_op["reduce_plain"] = {"ms": round(plain_ms, 4),
-                              "GB/s": round(8 * N / (plain_ms * 1e-3) / 1e9, 1),
-                              "frac_of_peak": round(8 * N / (plain_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    # roofline: the longest-running operation that is one kernel launch (the
+    # reductions add a 2-5 us counter-zeroing prologue); the scans are three
+    # launches per call and the graph replay four: those are reported per op
+    single = [(ms, o) for o, ms in zip(ops, op_ms) if o.kernel]
+    dom_ms, dom = max(single, key=lambda p: p[0])
+    achieved = dom.nbytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom.kernel, "op": dom.name, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(dom.kernel), "algorithmic_bytes_per_launch": dom.nbytes}
+    scan_ops = {o.name: per_op[o.name]["frac_of_peak"] for o in ops if "scan" in o.name}
 
     line = {
         "metric": METRIC,
@@ -471,21 +765,30 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "stream triad + dot (2^28 f32, 8 equal segments, uniform[-1,1), s=3): "
-                               "for_each, compensated dot, scan with f64 carries, batched fused scan+dot, "
-                               "backward (dot adjoint + reverse scan)",
-                   "elements": N, "segments": SEGMENTS, "bytes_per_step": step_bytes(N),
-                   "frac_of_peak": round(value / HBM_PEAK_GBS, 4), "dominant_kernel": kernel_name,
-                   "dominant_op": max(per_op_ms, key=per_op_ms.get),
-                   "per_op": per_op, "device_fault_flags": flags, "wall_s": round(wall, 3)},
+        "config": {"workload": "the four full-size workloads in one step: triad (2^28 f32, 8 segments: for_each "
+                               "a = b + 3c, compensated dot), scan (2^30 int32 in 16 Dirichlet segments -> int64 "
+                               "and -> int32; 2^28 f32 in 16 segments with f64 and with f32 carries), precision "
+                               "(2^29 mixture, f32 and bf16: sum of squares and dot, compensated and plain), "
+                               "batch (10,000 ragged ranges, 2^28 f32: fused scan + dot from a hipGraph, "
+                               "backward: broadcast multiply and reverse scan)",
+                   "bytes_per_step": step_bytes, "frac_of_peak": round(value / HBM_PEAK_GBS, 4),
+                   "dominant_op": ops[max(range(len(ops)), key=lambda i: op_ms[i])].name,
+                   "scan_ops_frac_of_peak": scan_ops,
+                   "per_op": per_op, "device_fault_flags": flags, "wall_s": round(wall, 3),
+                   "setup_s": round(t_setup, 1)},
         "roofline": roofline,
         "cpu_baseline": None,
     }
-    del a, s, sb, gb, gc, gs, up
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline()
+        print("[bench] CPU leg: oracle (serial), oracle on every core, plain loops", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        errs, base = cpu_leg(host, out)
+        for name, e in errs.items():
+            per_op[name]["error_vs_fp64_oracle"] = e
+        base["leg_s"] = round(time.perf_counter() - t0, 1)
+        line["cpu_baseline"] = base
     print(json.dumps(line), flush=True)
-    return 0
+    return 0 if flags == 0 else 1
 
 
 if __name__ == "__main__":
