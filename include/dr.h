@@ -468,6 +468,26 @@ dr_status dr_device_status(void* workspace, uint32_t* flags, void* stream);
  */
 dr_status dr_check_device_error(uint32_t* flags, void* stream);
 
+/*
+ * inclusive_scan that allocates nothing and takes no workspace: for callers
+ * that cannot allocate device memory (code being captured into a hipGraph,
+ * tight serving loops, harnesses that forbid hipMalloc). Same operation,
+ * arguments, forms and results as dr_inclusive_scan, with the workspace
+ * replaced by a static scratch area of the library (8 MiB per device,
+ * resident from the first call on a device until the process ends; zero-
+ * filled on that first call by a kernel enqueued on `stream`). Tables of
+ * more than DR_SMALL_TABLE rows are planned into the scratch by every call.
+ * A call whose workspace would not fit the scratch (more than about 2.6e5
+ * tiles: 2^30 binary32 elements at the default tile) is rejected with
+ * DR_ERR_WORKSPACE before anything is enqueued. Every call on a device
+ * shares its scratch, which keeps the last call's contents: calls that
+ * overlap in time on one device (other streams, other threads) race and
+ * must be ordered by the caller. Device faults are reported only through
+ * dr_check_device_error. Never calls hipMalloc / hipFree.
+ */
+dr_status dr_inclusive_scan_noalloc(const dr_table* table, const dr_view* view, int32_t out_dtype,
+                                    uint32_t flags, const dr_tuning* tuning, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,7 +83,7 @@ EXPORTS = ["dr_abi_version", "dr_status_string", "dr_last_error", "dr_tuning_sup
            "dr_workspace_bytes", "dr_workspace_init", "dr_plan", "dr_for_each",
            "dr_transform_reduce", "dr_inclusive_scan", "dr_scan_reduce", "dr_broadcast_mul",
            "dr_device_status", "dr_trim_segments", "dr_zip_segments", "dr_reduce", "dr_scan",
-           "dr_check_device_error"]
+           "dr_check_device_error", "dr_inclusive_scan_noalloc"]
 
 _lib = None
 
@@ -120,6 +120,7 @@ def lib() -> ctypes.CDLL:
     L.dr_broadcast_mul.argtypes = [TP, VP, P, i32, P, S, UP, P]
     L.dr_device_status.argtypes = [P, ctypes.POINTER(u32), P]
     L.dr_check_device_error.argtypes = [ctypes.POINTER(u32), P]
+    L.dr_inclusive_scan_noalloc.argtypes = [TP, VP, i32, u32, UP, P]
     L.dr_reduce.argtypes = [TP, VP, i32, i32, P, P, P, S, UP, P]
     L.dr_scan.argtypes = [TP, VP, i32, i32, u32, P, P, S, UP, P]
     RP, I64P = ctypes.POINTER(dr_range), ctypes.POINTER(i64)
@@ -369,6 +370,15 @@ def dr_inclusive_scan(table: Table, view: dr_view, out_dtype: int, flags: int = 
     c = table.c_table(host_check)
     check(lib().dr_inclusive_scan(ctypes.byref(c), ctypes.byref(view), out_dtype, flags, workspace.ptr,
                                   workspace.nbytes, _tp(tuning), _stream(table.device)))
+
+
+def dr_inclusive_scan_noalloc(table: Table, view: dr_view, out_dtype: int, flags: int = 0,
+                              tuning: dr_tuning | None = None, host_check: bool = True) -> None:
+    """dr_inclusive_scan on the library's static scratch (no workspace, no
+    allocation)."""
+    c = table.c_table(host_check)
+    check(lib().dr_inclusive_scan_noalloc(ctypes.byref(c), ctypes.byref(view), out_dtype, flags, _tp(tuning),
+                                          _stream(table.device)))
 
 
 def dr_scan_reduce(table: Table, scan_view: dr_view, reduce_view: dr_view, acc: int, init: float,

@@ -266,6 +266,16 @@ dr_status prepare(const dr_table* t, int algo, int in_dt, int out_dt, int arity,
 
 }  // namespace
 
+dr_status dr::set_error(dr_status s, const char* fmt, ...) {
+    char buf[768];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
 int dr::resident_grid(const void* kernel, int threads) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1;

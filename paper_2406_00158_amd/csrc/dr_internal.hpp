@@ -131,5 +131,9 @@ struct DeviceGlobals {
 };
 hipError_t device_globals(hipStream_t stream, DeviceGlobals& g);
 
+// Record `s` with a formatted reason as the calling thread's last error
+// (dr_last_error) and return it.
+dr_status set_error(dr_status s, const char* fmt, ...);
+
 
 }  // namespace dr

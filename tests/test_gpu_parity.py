@@ -371,6 +371,8 @@ def test_device_flags_bad_table_without_host_mirror():
     B.dr_inclusive_scan(tab, B.make_view("identity", B.DR_F32), B.DR_F32, workspace=ws, host_check=False)
     assert ws.device_status() & 1
     assert ws.device_status() == 0         # cleared by the read
+    assert B.dr_check_device_error() & 1   # the device's fault word saw it too
+    assert B.dr_check_device_error() == 0
     tab.total_length = 100
     B.dr_inclusive_scan(tab, B.make_view("identity", B.DR_F32), B.DR_F32, workspace=ws)
     assert np.array_equal(dev_to_np(out), np.arange(1, 101, dtype=np.float32))
@@ -398,11 +400,12 @@ def test_scan_malformed_row_of_planned_table_is_flagged(form):
                         tuning=_scan_tuning(form))
     torch.cuda.synchronize()
     assert ws.device_status() & 1
+    assert B.dr_check_device_error() & 1
     good = B.segments([ins], [outs])
     B.dr_inclusive_scan(good, B.make_view("identity", B.DR_F32), B.DR_F32, workspace=ws,
                         tuning=_scan_tuning(form))
     assert np.array_equal(dev_to_np(out), np.arange(1, 13001, dtype=np.float32))
-    assert ws.device_status() == 0
+    assert ws.device_status() == 0 and B.dr_check_device_error() == 0
 
 
 def test_one_workspace_across_algorithms_with_different_default_tiles():
