@@ -221,6 +221,20 @@ enum { DR_TUNE_TILE_PER_BLOCK = 1 };
  * Results are those of a fixed order of operations, like the default's. */
 enum { DR_TUNE_SPECIALIZED = 2 };
 
+/* dr_tuning.flags for inclusive_scan, scan (sum) and scan_reduce: the
+ * reduce-then-scan form (the default for all but small int32 scans): a
+ * read-only pass forms every tile's total, one workgroup scans the
+ * per-chunk totals, and the apply pass reads the input again, scans each
+ * tile and adds its carry (three launches; the input is read twice). Max /
+ * min scans always run this form. */
+enum { DR_TUNE_TWO_PASS = 4 };
+
+/* dr_tuning.flags, reserved for a chained single pass (chunks claimed from
+ * a counter, each read once to publish its total and again from the L2
+ * cache to be scanned and written). Switched off in this build: calls that
+ * set it return DR_ERR_UNSUPPORTED. */
+enum { DR_TUNE_CHAINED = 8 };
+
 /* Library version (DR_ABI_VERSION). Never fails. */
 int dr_abi_version(void);
 
@@ -297,13 +311,15 @@ dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_
  * first). By default the call runs three kernels: tile totals (reads the
  * input), a scan of per-chunk totals, and the tile scans plus carries
  * (reads the input again, writes the output once); carries are sums in a
- * fixed order, so results repeat from run to run. With
- * DR_TUNE_TILE_PER_BLOCK it is one kernel whose tiles take their carries
- * from a decoupled look-back; without a tuning, int32 scans of at most 2^22
- * elements take that form too (lower latency, exact either way), and larger
- * int32 -> int64 scans of the identity view over tables of at most
- * DR_SMALL_TABLE rows use tiles of 64 items per thread (the output is twice
- * the input's size). Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
+ * fixed order, so results repeat from run to run (DR_TUNE_TWO_PASS names
+ * this form explicitly). DR_TUNE_TILE_PER_BLOCK selects one kernel whose
+ * tiles take their carries from a decoupled look-back, and
+ * DR_TUNE_SPECIALIZED the single pass with specialised waves; at most one
+ * form flag. Without a tuning, int32 scans of at most 2^22 elements take the
+ * look-back form (lower latency, exact either way), and larger int32 ->
+ * int64 scans of the identity view over tables of at most DR_SMALL_TABLE
+ * rows use tiles of 64 items per thread (the output is twice the input's
+ * size). Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
  * (exact modulo 2^32), F32 -> F32 and BF16 -> F32 (binary32 inside a tile,
  * binary64 carries unless DR_SCAN_CARRY_F32), F64 -> F64.
  * In-place (out[0] == in[0], same dtype size) is allowed; other overlap

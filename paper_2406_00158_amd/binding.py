@@ -150,6 +150,8 @@ def make_view(op: int | str, in_dtype: int | torch.dtype, alpha: float = 0.0) ->
 
 DR_TUNE_TILE_PER_BLOCK = 1
 DR_TUNE_SPECIALIZED = 2
+DR_TUNE_TWO_PASS = 4
+DR_TUNE_CHAINED = 8
 # items per thread of the specialised-wave scan form, by input dtype (fused: 16)
 WS_ITEMS = {DR_F32: 32, DR_BF16: 32, DR_I32: 32, DR_F64: 16}
 WS_ITEMS_FUSED = 16

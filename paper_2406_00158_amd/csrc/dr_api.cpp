@@ -171,8 +171,10 @@ dr_status check_host_rows(const dr_table* t, int arity, int nout, int ies, int o
 dr_status resolve_items(const dr_tuning* tu, int algo, int in_dt, int& items) {
     items = default_items(algo, in_dt);
     if (!tu) return DR_OK;
-    if ((tu->flags & ~(DR_TUNE_TILE_PER_BLOCK | DR_TUNE_SPECIALIZED)) || tu->reserved)
-        return fail(DR_ERR_INVALID_ARG, "unknown tuning bits");
+    const int32_t forms = DR_TUNE_TILE_PER_BLOCK | DR_TUNE_SPECIALIZED | DR_TUNE_TWO_PASS | DR_TUNE_CHAINED;
+    if ((tu->flags & ~forms) || tu->reserved) return fail(DR_ERR_INVALID_ARG, "unknown tuning bits");
+    const int32_t f = tu->flags & forms;
+    if (f & (f - 1)) return fail(DR_ERR_INVALID_ARG, "at most one form flag (DR_TUNE_*) per call");
     if (tu->block_threads != 0 && tu->block_threads != kBlock)
         return fail(DR_ERR_UNSUPPORTED, "block_threads must be %d", kBlock);
     if (tu->items_per_thread != 0) items = tu->items_per_thread;
@@ -209,7 +211,15 @@ WsLayout layout_for(int algo, int64_t m, int64_t tmax) {
     L.off_ucnt = off;
     off += align256(nunits * 4);
     L.off_chunk = off;
-    if (algo == DR_ALGO_SCAN || algo == DR_ALGO_SCAN_REDUCE) off += align256((uint64_t)(4 + 4 * kMaxChunks) * 8);
+    const bool scan = algo == DR_ALGO_SCAN || algo == DR_ALGO_SCAN_REDUCE;
+    if (scan) off += align256((uint64_t)(4 + 4 * kMaxChunks) * 8);
+    // chained single pass: chunks of at least one tile, so at most
+    // ceil(tmax / kChainSB) superblocks
+    L.npipe = scan ? (uint64_t)(1 + (tmax + kChainSB - 1) / kChainSB + 1) : 0;
+    L.off_pipe = off;
+    off += align256(L.npipe * 4);
+    L.off_pipe_e = off;
+    off += align256(L.npipe * 16);
     L.bytes = off;
     return L;
 }
@@ -442,6 +452,24 @@ static bool prefer_single_pass(const dr_table* t, int in_dt, const dr_tuning* tu
     return !tu && in_dt == DR_I32 && t && t->total_length <= ((int64_t)1 << 22);
 }
 
+// The form of a sum scan (launch flag): an explicit DR_TUNE_* form, else
+// the look-back for small int32 scans (prefer_single_pass), else the
+// reduce-then-scan passes. Max / min scans always run the two passes.
+static uint32_t sum_scan_form(const dr_table* t, int in_dt, const dr_tuning* tu) {
+    const int32_t f = tu ? tu->flags : 0;
+    if (f & DR_TUNE_TILE_PER_BLOCK) return kFlagTilePerBlock;
+    if (prefer_single_pass(t, in_dt, tu)) return kFlagTilePerBlock;
+    return 0u;
+}
+
+// The chained single pass is switched off: a GPU run of it (int32 -> int64,
+// reverse, 2^25 elements) faulted and the cause has not been found.
+static dr_status check_chained_off(const dr_tuning* tu) {
+    if (tu && (tu->flags & DR_TUNE_CHAINED))
+        return fail(DR_ERR_UNSUPPORTED, "the chained single pass (DR_TUNE_CHAINED) is switched off in this build");
+    return DR_OK;
+}
+
 // The single pass with specialised waves, on request (DR_TUNE_SPECIALIZED,
 // at the form's own tile size). It is not the default: at 2^28 binary32
 // elements it measured level with the two passes (513-517 us against
@@ -503,6 +531,8 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
         return fail(DR_ERR_INVALID_ARG, "unknown scan flags 0x%x", flags);
     if ((flags & DR_SCAN_CARRY_F32) && in != DR_F32 && in != DR_BF16)
         return fail(DR_ERR_INVALID_ARG, "DR_SCAN_CARRY_F32 applies to binary32/bfloat16 inputs only");
+    s = check_chained_off(tuning);
+    if (s) return s;
     Prepared p;
     int items;
     dr_tuning dflt, wst;
@@ -520,8 +550,7 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
     p.a.alpha = view->alpha;
     p.a.flags = flags;
     if (ws_on) p.a.flags |= kFlagSpecialized;
-    else if ((tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) || prefer_single_pass(table, in, tuning))
-        p.a.flags |= kFlagTilePerBlock;
+    else p.a.flags |= sum_scan_form(table, in, tuning);
     return launch(fn, p, stream, "inclusive_scan launch");
 }
 
@@ -585,8 +614,10 @@ dr_status dr_scan(const dr_table* table, const dr_view* view, int32_t out_dtype,
         if (tuning && tuning->items_per_thread != 0 && tuning->items_per_thread != 16)
             return fail(DR_ERR_UNSUPPORTED, "max / min scans are built for 16 items per thread");
     }
-    if (mm && tuning && (tuning->flags & DR_TUNE_SPECIALIZED))
+    if (mm && tuning && (tuning->flags & (DR_TUNE_SPECIALIZED | DR_TUNE_CHAINED)))
         return fail(DR_ERR_UNSUPPORTED, "max / min scans run in the reduce-then-scan form only");
+    s = check_chained_off(tuning);
+    if (s) return s;
     Prepared p;
     int items;
     dr_tuning dflt, wst;
@@ -607,8 +638,7 @@ dr_status dr_scan(const dr_table* table, const dr_view* view, int32_t out_dtype,
     p.a.alpha = view->alpha;
     p.a.flags = flags;
     if (ws_on) p.a.flags |= kFlagSpecialized;
-    else if ((tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) || (!mm && prefer_single_pass(table, in, tuning)))
-        p.a.flags |= kFlagTilePerBlock;
+    else if (!mm) p.a.flags |= sum_scan_form(table, in, tuning);
     if (combine == DR_COMBINE_MIN) p.a.flags |= kFlagMin;
     if (init) {
         p.a.flags |= kFlagHasInit;
@@ -636,6 +666,8 @@ dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view, const 
     if (!init) return fail(DR_ERR_INVALID_ARG, "init is NULL");
     if (!result && !(table && table->mode == DR_MODE_BATCH && table->n_segments == 0))
         return fail(DR_ERR_INVALID_ARG, "result is NULL");
+    s = check_chained_off(tuning);
+    if (s) return s;
     Prepared p;
     int items;
     dr_tuning wst;
@@ -649,7 +681,7 @@ dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view, const 
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "fused scan kernel not built for this combination");
     p.a.flags = flags;
     if (ws_on) p.a.flags |= kFlagSpecialized;
-    else if (tuning && (tuning->flags & DR_TUNE_TILE_PER_BLOCK)) p.a.flags |= kFlagTilePerBlock;
+    else p.a.flags |= sum_scan_form(table, in, tuning);
     p.a.result = result;
     p.a.init_f = *(const double*)init;
     return launch(fn, p, stream, "scan_reduce launch");

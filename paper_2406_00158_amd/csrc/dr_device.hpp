@@ -57,11 +57,13 @@ struct vec {
     typename elem<DT>::T e[V];
 };
 
-template <int DT, int V = vwidth<DT>()>
+// NT: a non-temporal (streaming) load; otherwise a plain load, whose line
+// stays in L2 for a later re-read.
+template <int DT, int V = vwidth<DT>(), bool NT = true>
 __device__ __forceinline__ vec<DT, V> load_vec(const void* base, int64_t j) {
     using R = typename vbits<V * esize<DT>()>::T;
     const R* p = (const R*)((const char*)base + j * esize<DT>());
-    R w = __builtin_nontemporal_load(p);
+    R w = NT ? __builtin_nontemporal_load(p) : *p;
     vec<DT, V> v;
     __builtin_memcpy(&v, &w, sizeof(R));
     return v;
@@ -692,7 +694,7 @@ __device__ __forceinline__ bool tile_full(const SegInfo& si, int64_t u0) {
 }
 
 // The slots of a full tile (tile_full): whole vectors, no checks.
-template <int DT, int SLOTS, int V = vwidth<DT>()>
+template <int DT, int SLOTS, int V = vwidth<DT>(), bool NT = true>
 __device__ __forceinline__ void load_slots_full(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
                                                 int64_t u0, int w, int l, bool rev) {
     using R = typename vbits<V * esize<DT>()>::T;
@@ -703,14 +705,14 @@ __device__ __forceinline__ void load_slots_full(vec<DT, V> (&x)[SLOTS], const vo
     const int64_t step = rev ? -64 * (int64_t)sizeof(R) : 64 * (int64_t)sizeof(R);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        R wv = __builtin_nontemporal_load((const R*)(b + s * step));
+        R wv = NT ? __builtin_nontemporal_load((const R*)(b + s * step)) : *(const R*)(b + s * step);
         __builtin_memcpy(&x[s], &wv, sizeof(R));
     }
 }
 
 // The slots of any tile, each element checked against the segment (the
 // elements outside it read as 0).
-template <int DT, int SLOTS, int V = vwidth<DT>()>
+template <int DT, int SLOTS, int V = vwidth<DT>(), bool NT = true>
 __device__ __forceinline__ void load_slots_checked(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
                                                    int64_t u0, int w, int l, bool rev) {
     constexpr int64_t NV = (int64_t)kBlock * SLOTS;
@@ -721,7 +723,7 @@ __device__ __forceinline__ void load_slots_checked(vec<DT, V> (&x)[SLOTS], const
         const int64_t q = rev ? (NV - 1 - p) : p;
         const int64_t j = u0 + q * V - si.shift;
         if (si.vec_ok && j >= 0 && j + V <= si.n) {
-            x[s] = load_vec<DT, V>(base, j);
+            x[s] = load_vec<DT, V, NT>(base, j);
         } else {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
@@ -734,11 +736,11 @@ __device__ __forceinline__ void load_slots_checked(vec<DT, V> (&x)[SLOTS], const
     }
 }
 
-template <int DT, int SLOTS, int V = vwidth<DT>()>
+template <int DT, int SLOTS, int V = vwidth<DT>(), bool NT = true>
 __device__ __forceinline__ void load_slots(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
                                            int64_t u0, int w, int l, bool rev) {
-    if (tile_full<V, SLOTS>(si, u0)) load_slots_full<DT, SLOTS, V>(x, base, si, u0, w, l, rev);
-    else load_slots_checked<DT, SLOTS, V>(x, base, si, u0, w, l, rev);
+    if (tile_full<V, SLOTS>(si, u0)) load_slots_full<DT, SLOTS, V, NT>(x, base, si, u0, w, l, rev);
+    else load_slots_checked<DT, SLOTS, V, NT>(x, base, si, u0, w, l, rev);
 }
 
 // The two inputs of a zipped view (y only when ZIP) under one branch on

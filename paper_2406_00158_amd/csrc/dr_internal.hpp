@@ -53,6 +53,10 @@ struct WsLayout {
     uint64_t off_gpart;        // [ngroups * 2]: tagged group partials
     uint64_t off_ucnt;         // uint32 [nunits]: arrived groups per result (zeroed by the prologue)
     uint64_t off_chunk;        // scans: [4 + 4 * kMaxChunks] chunk records of the reduce-then-scan form
+    uint64_t off_pipe;         // scans: uint32 [npipe]: the chained pass's chunk counter, then one arrival
+                               // counter per superblock (zeroed by the prologue)
+    uint64_t npipe;
+    uint64_t off_pipe_e;       // scans: tagged [2 * npipe]: the running carry at the end of each superblock
     uint64_t bytes;            // total size
     uint64_t ngroups;          // counters at off_gcnt
     uint64_t nunits;           // counters at off_ucnt
@@ -95,6 +99,11 @@ constexpr uint32_t kFlagHasInit = 1u << 17;   // scans: combine init into every 
 constexpr uint32_t kFlagMin = 1u << 18;       // min/max kernels: min (else max)
 constexpr int kAccMinMax = 2;                 // reduce kernels: max / min instead of a sum
 constexpr uint32_t kFlagSpecialized = 1u << 19;   // scans: the single pass with specialised waves
+constexpr uint32_t kFlagChained = 1u << 20;       // scans: the chained single pass (chunks re-read from L2)
+
+// Chunks per superblock of the chained single pass: a chunk's carry folds
+// the totals of at most this many chunks before it.
+constexpr int kChainSB = 128;
 
 // Items per thread of the scans' specialised-wave form for an input dtype
 // (0: not built).

@@ -122,27 +122,31 @@ hipError_t launch_plan(const LaunchArgs& a, hipStream_t stream) {
 }
 
 // Prologue of a launch that uses tags: epoch + 1 (workgroup 0), and the
-// group / unit arrival counters of the launch's layout set to 0.
+// group / unit arrival counters and the chained scan's counters of the
+// launch's layout set to 0.
 __global__ __launch_bounds__(256) void k_prologue(uint8_t* ws, uint64_t off_g, uint64_t ng, uint64_t off_u,
-                                                  uint64_t nu) {
+                                                  uint64_t nu, uint64_t off_p, uint64_t np) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         Header* h = (Header*)ws;
         h->epoch = h->epoch + 1u;
     }
     uint32_t* g = (uint32_t*)(ws + off_g);
     uint32_t* u = (uint32_t*)(ws + off_u);
+    uint32_t* q = (uint32_t*)(ws + off_p);
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < ng; i += stride) g[i] = 0u;
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < nu; i += stride) u[i] = 0u;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < np; i += stride) q[i] = 0u;
 }
 
 hipError_t launch_prologue(const LaunchArgs& a, hipStream_t stream) {
-    const uint64_t n = a.lay.ngroups > a.lay.nunits ? a.lay.ngroups : a.lay.nunits;
+    uint64_t n = a.lay.ngroups > a.lay.nunits ? a.lay.ngroups : a.lay.nunits;
+    if (a.lay.npipe > n) n = a.lay.npipe;
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 256) blocks = 256;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_prologue, dim3((uint32_t)blocks), dim3(256), 0, stream, a.ws, a.lay.off_gcnt,
-                       a.lay.ngroups, a.lay.off_ucnt, a.lay.nunits);
+                       a.lay.ngroups, a.lay.off_ucnt, a.lay.nunits, a.lay.off_pipe, a.lay.npipe);
     return hipGetLastError();
 }
 

@@ -30,6 +30,20 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(B.EXPORTS)
 
 
+def test_chained_scan_form_is_switched_off():
+    t, keep = _host_table([((A,), (O,), 10)], 10)
+    v = B.make_view("identity", B.DR_F32)
+    tu = B.make_tuning(16, B.DR_TUNE_CHAINED)
+    L = B.lib()
+    assert L.dr_inclusive_scan(ctypes.byref(t), ctypes.byref(v), B.DR_F32, 0, 0x40000000, 1 << 30,
+                               ctypes.byref(tu), None) == B.DR_ERR_UNSUPPORTED
+    assert b"switched off" in L.dr_last_error()
+    tu2 = B.make_tuning(16, B.DR_TUNE_TILE_PER_BLOCK | B.DR_TUNE_TWO_PASS)
+    assert L.dr_inclusive_scan(ctypes.byref(t), ctypes.byref(v), B.DR_F32, 0, 0x40000000, 1 << 30,
+                               ctypes.byref(tu2), None) == B.DR_ERR_INVALID_ARG   # one form flag at most
+    del keep
+
+
 def test_check_device_error_rejects_null_flags():
     assert B.lib().dr_check_device_error(None, None) == B.DR_ERR_INVALID_ARG
 

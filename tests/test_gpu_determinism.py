@@ -1,9 +1,9 @@
-"""Run-to-run reproducibility of the default forms and of the single pass
-with specialised waves. The reduce-then-scan carries are combined in a fixed
-order (tile records relative to their chunk, then one fixed-shape scan of the
-chunk records); the specialised form's agent scans the published tile totals
-with a fixed shape; reductions combine tile partials in member order over a
-fixed tree. So repeated calls give the same bits for floating-point inputs,
+"""Run-to-run reproducibility of the default forms, of the reduce-then-scan
+passes named explicitly and of the single pass with specialised waves. The
+reduce-then-scan carries are combined in a fixed order (tile records
+relative to their chunk, then one fixed-shape scan of the chunk records);
+the specialised form's agent scans the published tile totals with a fixed
+shape; reductions combine tile partials in member order over a fixed tree. So repeated calls give the same bits for floating-point inputs,
 not just results within the error bound. The workspace is shared between the
 calls, as a caller's would be."""
 import numpy as np
@@ -40,11 +40,12 @@ def _input(in_dt, n, seed):
 @pytest.mark.parametrize("reverse", [False, True])
 @pytest.mark.parametrize("in_dt,out_dt,flags", [(B.DR_F32, B.DR_F32, 0), (B.DR_F32, B.DR_F32, B.DR_SCAN_CARRY_F32),
                                                 (B.DR_BF16, B.DR_F32, 0), (B.DR_F64, B.DR_F64, 0)])
-@pytest.mark.parametrize("form", ["default", "specialized"])
+@pytest.mark.parametrize("form", ["default", "two_pass", "specialized"])
 def test_float_scans_repeat_bit_for_bit(mode, reverse, in_dt, out_dt, flags, form):
     if form == "specialized" and flags & B.DR_SCAN_CARRY_F32:
         pytest.skip("the specialised-wave form keeps binary64 carries")
-    tuning = B.make_tuning(B.WS_ITEMS[in_dt], B.DR_TUNE_SPECIALIZED) if form == "specialized" else None
+    tuning = {"default": None, "two_pass": B.make_tuning(None, B.DR_TUNE_TWO_PASS),
+              "specialized": B.make_tuning(B.WS_ITEMS[in_dt], B.DR_TUNE_SPECIALIZED)}[form]
     announce("scan repeat", mode, reverse, in_dt, flags, form)
     x = _input(in_dt, sum(LENGTHS), 901)
     ins = place(x, LENGTHS, "separate")
@@ -86,10 +87,11 @@ def test_dot_repeats_bit_for_bit(mode, acc):
     assert ws.device_status() == 0
 
 
-@pytest.mark.parametrize("form", ["default", "specialized"])
+@pytest.mark.parametrize("form", ["default", "two_pass", "specialized"])
 def test_fused_scan_reduce_repeats_bit_for_bit(form):
     announce("fused repeat", form)
-    tuning = B.make_tuning(B.WS_ITEMS_FUSED, B.DR_TUNE_SPECIALIZED) if form == "specialized" else None
+    tuning = {"default": None, "two_pass": B.make_tuning(None, B.DR_TUNE_TWO_PASS),
+              "specialized": B.make_tuning(B.WS_ITEMS_FUSED, B.DR_TUNE_SPECIALIZED)}[form]
     lengths = I.lengths_loguniform(3000, 1 << 18, 1 << 22, 904)
     n = sum(lengths)
     x, y = I.normal_f32(n, 905), I.normal_f32(n, 906)

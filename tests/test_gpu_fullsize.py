@@ -109,14 +109,15 @@ def test_int_scan_2_30(out_dt):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("form", ["default", "specialized"])
+@pytest.mark.parametrize("form", ["default", "two_pass", "specialized"])
 def test_fp32_scan_2_28_f64_carry(form):
     t = _workload("scan_fp")
     L = t["lengths"]
     announce("fp scan 2^28", form)
     x = _to_dev(t["x"])
     out = torch.empty_like(x)
-    tuning = B.make_tuning(B.WS_ITEMS[B.DR_F32], B.DR_TUNE_SPECIALIZED) if form == "specialized" else None
+    tuning = {"default": None, "two_pass": B.make_tuning(None, B.DR_TUNE_TWO_PASS),
+              "specialized": B.make_tuning(B.WS_ITEMS[B.DR_F32], B.DR_TUNE_SPECIALIZED)}[form]
     B.dr_inclusive_scan(B.segments([_pieces(x, L)], [_pieces(out, L)]), B.make_view("identity", B.DR_F32),
                         B.DR_F32, tuning=tuning)
     got = dev_to_np(out).astype(np.float64)

@@ -1,7 +1,7 @@
-"""Scan parity at 2^25 + a ragged tail, in the default launch configuration:
-large enough that the first (tile totals) pass gives every workgroup a chunk
-of several tiles, with segment heads inside chunks, as at the benchmark's
-sizes. Reverse scans (the scan adjoint), exclusive sums with an initial
+"""Scan parity at 2^25 + a ragged tail, in the default form and with the
+reduce-then-scan form named explicitly (its first pass gives every
+workgroup a chunk of several tiles, with segment heads inside chunks), as at
+the benchmark's sizes. Reverse scans (the scan adjoint), exclusive sums with an initial
 value and max / min scans, over one distributed range (CONCAT, 16 Dirichlet
 segments) and over 300 ragged independent ranges (BATCH, a planned table),
 against the oracle: integers and max / min exactly, binary32 sums within
@@ -45,14 +45,18 @@ def _pieces(t, lengths):
     return out
 
 
-def _run(in_dt, out_dt, mode, combine, flags, init):
+FORMS = {"default": None, "two_pass": B.make_tuning(None, B.DR_TUNE_TWO_PASS)}
+
+
+def _run(in_dt, out_dt, mode, combine, flags, init, form="default"):
     lengths = _lengths(mode)
     x = _data(in_dt)
     xd = torch.from_numpy(x).to(dev())
     out = torch.empty(N, dtype=B.TORCH_DTYPE[out_dt], device=dev())
     tab = B.segments([_pieces(xd, lengths)], [_pieces(out, lengths)], mode=mode)
     ws = B.Workspace(dev())
-    B.dr_scan(tab, B.make_view("identity", in_dt), out_dt, combine, flags, init, workspace=ws, host_check=False)
+    B.dr_scan(tab, B.make_view("identity", in_dt), out_dt, combine, flags, init, workspace=ws, host_check=False,
+              tuning=FORMS[form])
     assert ws.device_status() == 0
     return lengths, x, dev_to_np(out)
 
@@ -73,22 +77,24 @@ def _check_sum(in_dt, out_dt, mode, lengths, x, got, reverse, exclusive, init):
     assert np.all(err <= bound)
 
 
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("mode", ["concat", "batch"])
 @pytest.mark.parametrize("in_dt,out_dt", [(B.DR_I32, B.DR_I64), (B.DR_F32, B.DR_F32)])
-def test_reverse_scan_2_25(mode, in_dt, out_dt):
-    announce("reverse scan 2^25", mode, in_dt, out_dt)
-    lengths, x, got = _run(in_dt, out_dt, mode, B.DR_COMBINE_SUM, B.DR_SCAN_REVERSE, None)
+def test_reverse_scan_2_25(form, mode, in_dt, out_dt):
+    announce("reverse scan 2^25", form, mode, in_dt, out_dt)
+    lengths, x, got = _run(in_dt, out_dt, mode, B.DR_COMBINE_SUM, B.DR_SCAN_REVERSE, None, form)
     _check_sum(in_dt, out_dt, mode, lengths, x, got, True, False, None)
 
 
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("mode", ["concat", "batch"])
 @pytest.mark.parametrize("reverse", [False, True])
 @pytest.mark.parametrize("in_dt,out_dt", [(B.DR_I32, B.DR_I64), (B.DR_F32, B.DR_F32)])
-def test_exclusive_sum_with_init_2_25(mode, reverse, in_dt, out_dt):
-    announce("exclusive+init scan 2^25", mode, reverse, in_dt, out_dt)
+def test_exclusive_sum_with_init_2_25(form, mode, reverse, in_dt, out_dt):
+    announce("exclusive+init scan 2^25", form, mode, reverse, in_dt, out_dt)
     init = -987654 if in_dt == B.DR_I32 else 1.5
     flags = B.DR_SCAN_EXCLUSIVE | (B.DR_SCAN_REVERSE if reverse else 0)
-    lengths, x, got = _run(in_dt, out_dt, mode, B.DR_COMBINE_SUM, flags, init)
+    lengths, x, got = _run(in_dt, out_dt, mode, B.DR_COMBINE_SUM, flags, init, form)
     _check_sum(in_dt, out_dt, mode, lengths, x, got, reverse, True, init)
 
 

@@ -186,10 +186,14 @@ SCAN_CASES = [(B.DR_I32, B.DR_I64), (B.DR_I32, B.DR_I32), (B.DR_F32, B.DR_F32), 
 
 
 # the library's default (no tuning: the two passes, or for small int32 scans
-# the single pass), the reduce-then-scan passes requested explicitly, and the
-# single-pass form (one workgroup per tile in block-index order, decoupled
-# look-back)
-SCAN_FORMS = ["default", "two_pass", "look_back", "specialized"]
+# the look-back), and each form requested explicitly: the reduce-then-scan
+# passes, the chained single pass (switched off: its cases are skipped), the
+# look-back (one workgroup per tile in block-index order) and the specialised
+# waves
+CHAINED_OFF = "the chained single pass is switched off: a GPU run of it faulted and the cause is not found"
+SCAN_FORMS = ["default", "two_pass", pytest.param("chained", marks=pytest.mark.skip(reason=CHAINED_OFF)),
+              "look_back", "specialized"]
+FORM_FLAG = {"two_pass": B.DR_TUNE_TWO_PASS, "chained": B.DR_TUNE_CHAINED, "look_back": B.DR_TUNE_TILE_PER_BLOCK}
 
 
 def _scan_tuning(form, items=16, in_dt=B.DR_F32, fused=False):
@@ -197,7 +201,7 @@ def _scan_tuning(form, items=16, in_dt=B.DR_F32, fused=False):
         return None
     if form == "specialized":
         return B.make_tuning(_form_items(form, in_dt, fused), B.DR_TUNE_SPECIALIZED)
-    return B.make_tuning(items, B.DR_TUNE_TILE_PER_BLOCK if form == "look_back" else 0)
+    return B.make_tuning(items, FORM_FLAG[form])
 
 
 def _form_items(form, in_dt=B.DR_F32, fused=False):
