@@ -74,6 +74,28 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def cpu_topology() -> dict:
+    """What `lscpu` reports of the host (model, sockets, cores, threads,
+    clock), with the CPUs this process may run on."""
+    import subprocess
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        want = ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)", "CPU max MHz",
+                "L3 cache", "NUMA node(s)")
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in want:
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        info["usable_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        info["usable_cpus"] = os.cpu_count()
+    return info
+
+
 # ---------------------------------------------------------------------------
 # The step
 # ---------------------------------------------------------------------------
@@ -91,6 +113,7 @@ def setup(dev):
     import numpy as np
     import torch
 
+    from paper_2406_00158_amd import autotune as AT
     from paper_2406_00158_amd import binding as B
     from paper_2406_00158_amd import inputs as I
 
@@ -108,6 +131,16 @@ def setup(dev):
 
     host, out, ops = {}, {}, []
     f32, v_id = B.DR_F32, B.make_view("identity", B.DR_F32)
+    tuning = out["tuning"] = {}
+
+    def tuned(name, algo, view, odt, table, call, extra=""):
+        """The autotuner's shape for `call` (timed now, outside the timed
+        region), recorded with every candidate's time."""
+        tu = AT.tune(algo, view, odt, table, call, extra=extra)
+        e = AT.entry(algo, view, odt, table, extra) or {}
+        tuning[name] = {"choice": AT.label(tu) if tu is not None else "default",
+                        "candidates_ms": {k: round(v, 4) for k, v in (e.get("all") or {}).items()}}
+        return tu
 
     # triad: 2^28 binary32, 8 equal segments
     t = I.triad()
@@ -204,10 +237,17 @@ def setup(dev):
     s5 = torch.empty_like(x5)
     r5 = torch.zeros(len(L5), dtype=torch.float64, device=dev)
     out["batch_s"], out["batch_r"] = s5, r5
+    out["batch_x"], out["batch_y"] = x5, y5
     ws5, ws5b, ws5r = B.Workspace(dev), B.Workspace(dev), B.Workspace(dev)
     t5 = B.segments([pieces(x5, L5), pieces(y5, L5)], [pieces(s5, L5)], mode="batch")
+    # the launch shape (workgroup size x items per thread x scan form) of the
+    # batch's two scans comes from the autotuner, timed here, before capture
+    tu5 = tuned("batch: fused scan + dot per range (hipGraph replay)", B.DR_ALGO_SCAN_REDUCE, v_id, f32, t5,
+                lambda tu: B.dr_scan_reduce(t5, v_id, v_mul, B.DR_ACC_COMPENSATED, 0.0, r5, workspace=ws5,
+                                            host_check=False, tuning=tu))
     fused = lambda: B.dr_scan_reduce(t5, v_id, v_mul, B.DR_ACC_COMPENSATED, 0.0, r5, workspace=ws5,
-                                     host_check=False)
+                                     host_check=False, tuning=tu5)
+    out["batch_tuning"] = tu5
     fused()                                 # eager: plans and sizes the workspace
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
@@ -230,12 +270,45 @@ def setup(dev):
     ops.append(Op("batch: backward, dot adjoint (broadcast multiply)", 16 * n5,
                   lambda: B.dr_broadcast_mul(tbm, v_mul, g5, 2, workspace=ws5b, host_check=False),
                   "k_broadcast_mul<1, 2, 16, 2>"))
+    tu5r = tuned("batch: backward, scan adjoint (reverse scan)", B.DR_ALGO_SCAN, v_id, f32, trs,
+                 lambda tu: B.dr_inclusive_scan(trs, v_id, f32, B.DR_SCAN_REVERSE, workspace=ws5r,
+                                                host_check=False, tuning=tu), extra="reverse")
     ops.append(Op("batch: backward, scan adjoint (reverse scan)", 8 * n5,
                   lambda: B.dr_inclusive_scan(trs, v_id, f32, B.DR_SCAN_REVERSE, workspace=ws5r,
-                                              host_check=False)))
+                                              host_check=False, tuning=tu5r)))
     out["workspaces"] = [ws2, ws3, ws4, ws5, ws5b, ws5r]
     out["graph"] = graph
     return ops, host, out
+
+
+def per_range_leg(host, out, dev, sample: int = 64) -> dict:
+    """The batch workload's fused scan + dot run again, outside the timed
+    region, on one-row tables for `sample` seeded ranges (with the batched
+    call's launch shape): the per-range results that the accuracy record
+    compares with the batched ones."""
+    import numpy as np
+    import torch
+
+    from paper_2406_00158_amd import binding as B
+
+    L = host["batch"]["lengths"]
+    offs = np.concatenate([[0], np.cumsum(L)]).astype(np.int64)
+    idx = sorted(int(i) for i in np.random.default_rng(1107).choice(len(L), size=sample, replace=False))
+    x5, y5 = out["batch_x"], out["batch_y"]
+    vid, vmul = B.make_view("identity", B.DR_F32), B.make_view("mul", B.DR_F32)
+    ws = B.Workspace(dev)
+    s_list, r_list = [], []
+    for i in idx:
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        s = torch.empty(hi - lo, dtype=torch.float32, device=dev)
+        r = torch.zeros(1, dtype=torch.float64, device=dev)
+        B.dr_scan_reduce(B.segments([[x5[lo:hi]], [y5[lo:hi]]], [[s]]), vid, vmul, B.DR_ACC_COMPENSATED, 0.0, r,
+                         workspace=ws, host_check=False, tuning=out.get("batch_tuning"))
+        s_list.append(s)
+        r_list.append(r)
+    torch.cuda.synchronize()
+    return {"idx": idx, "offs": offs, "s": [t.cpu().numpy() for t in s_list], "r": [t.item() for t in r_list],
+            "status": ws.device_status()}
 
 
 # ---------------------------------------------------------------------------
@@ -243,8 +316,10 @@ def setup(dev):
 # core, and plain binary32 loops
 # ---------------------------------------------------------------------------
 
-def cpu_leg(host, out, reps_parallel: int = 1) -> tuple[dict, dict]:
-    """Returns (errors by op name, cpu_baseline)."""
+def cpu_leg(host, out, per_range=None) -> tuple[dict, dict]:
+    """Returns (errors by op name, cpu_baseline). With `per_range` (from
+    per_range_leg) the batch entry also compares the per-range results with
+    the batched ones."""
     import numpy as np
 
     import oracle as O
@@ -328,13 +403,36 @@ def cpu_leg(host, out, reps_parallel: int = 1) -> tuple[dict, dict]:
     xl, yl = I.split(t["x"], L), I.split(t["y"], L)
     ref, absp = timed(lambda: O.scan(xl, None, O.F32, O.IDENTITY, mode=O.BATCH, want_abs=True))
     ref, absp = np.concatenate(ref), np.concatenate(absp)
-    e_scan = scan_metrics(d2h(out["batch_s"]), ref, absp)
-    del ref, absp
+    got_s = d2h(out["batch_s"])
+    e_scan = scan_metrics(got_s, ref, absp)
     w, m = timed(lambda: O.reduce(xl, yl, O.F32, O.MUL, mode=O.BATCH))
     got = d2h(out["batch_r"])
     r_err = np.abs(got - w) / np.maximum(np.abs(w), 1e-300)
     e_scan.update({"dot_max_rel_err": float(r_err.max()), "dot_median_rel_err": float(np.median(r_err)),
                    "dot_max_cond": float(np.max(m / np.maximum(np.abs(w), 1e-300)))})
+    if per_range is not None:
+        # the sampled ranges alone (one-row tables) beside the batched call
+        offs, eq, n_el, d_pref, e_one, e_bat, d_dot, re_one, re_bat = per_range["offs"], 0, 0, 0.0, 0.0, 0.0, \
+            0.0, 0.0, 0.0
+        for j, i in enumerate(per_range["idx"]):
+            lo, hi = int(offs[i]), int(offs[i + 1])
+            one, bat, a_i = per_range["s"][j], got_s[lo:hi], np.maximum(absp[lo:hi], 1e-300)
+            eq += int(np.sum(one.view(np.uint32) == bat.view(np.uint32)))
+            n_el += hi - lo
+            d_pref = max(d_pref, float(np.max(np.abs(one.astype(np.float64) - bat) / a_i)))
+            e_one = max(e_one, float(np.max(np.abs(one.astype(np.float64) - ref[lo:hi]) / a_i)))
+            e_bat = max(e_bat, float(np.max(np.abs(bat.astype(np.float64) - ref[lo:hi]) / a_i)))
+            r1, rb = per_range["r"][j], float(got[i])
+            d_dot = max(d_dot, abs(r1 - rb) / max(abs(rb), 1e-300))
+            re_one = max(re_one, abs(r1 - w[i]) / max(abs(w[i]), 1e-300))
+            re_bat = max(re_bat, abs(rb - w[i]) / max(abs(w[i]), 1e-300))
+        e_scan["per_range_vs_batched"] = {
+            "ranges": len(per_range["idx"]), "elements": n_el, "scan_frac_bitwise_equal": eq / max(n_el, 1),
+            "scan_max_diff_over_abs_prefix": d_pref, "scan_max_err_over_abs_prefix_per_range": e_one,
+            "scan_max_err_over_abs_prefix_batched": e_bat, "dot_max_rel_diff": d_dot,
+            "dot_max_rel_err_per_range": re_one, "dot_max_rel_err_batched": re_bat,
+            "device_status": per_range["status"]}
+    del ref, absp, got_s
     err["batch: fused scan + dot per range (hipGraph replay)"] = e_scan
     g = host["batch_g"]
     mism = 0
@@ -414,13 +512,65 @@ def cpu_leg(host, out, reps_parallel: int = 1) -> tuple[dict, dict]:
             "sample": f"the whole step once (every operation of the four workloads at full size: {work / 1e9:.1f} GB "
                       f"of algorithmic bytes, with the C4 plain/compensated pairs sharing one reference each), "
                       f"the binary64 / int64 oracle (gcc -O2) on all {nthreads} host threads: {t_par:.2f} s",
-            "cpu_model": cpu_model(),
+            "cpu_model": cpu_model(), "lscpu": cpu_topology(),
             "serial": {"value": gbs(t_serial), "cores": 1, "seconds": round(t_serial, 2),
                        "what": "the same oracle calls on one thread (they produced the error references)"},
             "plain_f32_loop": {"value": gbs(t_plain), "cores": 1, "seconds": round(t_plain, 2),
                                "what": "plain serial binary32 / int64 loops over the same operations (no "
                                        "binary64, no compensation): the cost of the arithmetic alone"}}
     return err, base
+
+
+def write_accuracy(path: str, line: dict, device_name: str) -> None:
+    """The accuracy record of one bench run: every result of the step
+    against the binary64 / int64 oracle, as a markdown file."""
+    per_op = line["config"]["per_op"]
+    u32 = 2.0 ** -24
+    fmt = lambda v: f"{v:.2e}" if isinstance(v, float) else str(v)
+    rows = ["# Accuracy of the bench step against the binary64 oracle", "",
+            f"`python bench.py {' '.join(sys.argv[1:])}` on {device_name}; kernel sources `{sources_hash()}`.",
+            "Every result of one step, compared on the host with the oracle's binary64 (integers: int64) result",
+            "on the same seeded inputs. Condition number of a sum: sum of |terms| / |sum|. A_i: the exact sum of",
+            "|x_j| over the prefix of element i (the scale of a prefix's rounding error).", "",
+            "## Exact results", "", "| operation | bit-exact | mismatching elements |", "|---|---|---|"]
+    for name, o in per_op.items():
+        e = o.get("error_vs_fp64_oracle", {})
+        if "bit_exact" in e:
+            rows.append(f"| {name} | {e['bit_exact']} | {e['mismatches']} |")
+    rows += ["", "## Reductions: plain vs compensated accumulation", "",
+             "| operation | relative error | condition number | u32 x condition |", "|---|---|---|---|"]
+    for name, o in per_op.items():
+        e = o.get("error_vs_fp64_oracle", {})
+        if "rel_err" in e:
+            rows.append(f"| {name} | {fmt(e['rel_err'])} | {fmt(e['cond'])} | {fmt(u32 * e['cond'])} |")
+    rows += ["", "## Scans: binary64 vs binary32 carries, batched", "",
+             "| operation | max abs error | max error / A_i | elements equal to the rounded exact prefix |",
+             "|---|---|---|---|"]
+    for name, o in per_op.items():
+        e = o.get("error_vs_fp64_oracle", {})
+        if "max_err_over_abs_prefix" in e:
+            rows.append(f"| {name} | {fmt(e['max_abs_err'])} | {fmt(e['max_err_over_abs_prefix'])} | "
+                        f"{e['frac_equal_fl32_ref']:.3f} |")
+    for name, o in per_op.items():
+        e = o.get("error_vs_fp64_oracle", {})
+        if "dot_max_rel_err" in e:
+            rows += ["", f"Per-range dots of `{name}`: max relative error {fmt(e['dot_max_rel_err'])}, median "
+                         f"{fmt(e['dot_median_rel_err'])}, largest condition number {fmt(e['dot_max_cond'])}."]
+        pr = e.get("per_range_vs_batched")
+        if pr:
+            rows += ["", "## Batched vs per-range", "",
+                     f"{pr['ranges']} seeded ranges ({pr['elements']} elements) of the batch workload, each run "
+                     "alone as a one-row table, beside the same ranges of the batched call:", "",
+                     "| quantity | per-range calls | batched call |", "|---|---|---|",
+                     f"| scan: max error / A_i | {fmt(pr['scan_max_err_over_abs_prefix_per_range'])} | "
+                     f"{fmt(pr['scan_max_err_over_abs_prefix_batched'])} |",
+                     f"| dot: max relative error | {fmt(pr['dot_max_rel_err_per_range'])} | "
+                     f"{fmt(pr['dot_max_rel_err_batched'])} |", "",
+                     f"Scan outputs bitwise equal between the two: {pr['scan_frac_bitwise_equal']:.6f} of the "
+                     f"elements (largest difference {fmt(pr['scan_max_diff_over_abs_prefix'])} A_i); dots: largest "
+                     f"relative difference {fmt(pr['dot_max_rel_diff'])}."]
+    with open(path, "w") as f:
+        f.write("\n".join(rows) + "\n")
 
 
 # ---------------------------------------------------------------------------
@@ -666,6 +816,9 @@ def main() -> int:
     ap.add_argument("--copy-only", action="store_true",
                     help="run only a plain copy (for_each identity, 2^28 f32) K times: the known-size "
                          "kernel that calibrates the HBM byte counters")
+    ap.add_argument("--accuracy", metavar="PATH",
+                    help="also write the accuracy record (every result against the binary64 oracle) as "
+                         "markdown to PATH (needs the CPU leg)")
     ap.add_argument("--configs", action="store_true",
                     help="time every workload alone at full size and print one JSON line per case instead "
                          "of the step line")
@@ -698,6 +851,9 @@ def main() -> int:
         print(json.dumps({"copy_bytes_per_launch": 8 * N, "launches": args.warmup + args.steps}), flush=True)
         return 0
 
+    if not os.environ.get("DR_TUNE_CACHE"):
+        import tempfile
+        os.environ["DR_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="dr_tune_"), "tune.json")
     t_setup = time.perf_counter()
     print("[bench] generating the seeded inputs of the four workloads", file=sys.stderr, flush=True)
     ops, host, out = setup(dev)
@@ -774,20 +930,30 @@ def main() -> int:
                    "bytes_per_step": step_bytes, "frac_of_peak": round(value / HBM_PEAK_GBS, 4),
                    "dominant_op": ops[max(range(len(ops)), key=lambda i: op_ms[i])].name,
                    "scan_ops_frac_of_peak": scan_ops,
-                   "per_op": per_op, "device_fault_flags": flags, "wall_s": round(wall, 3),
+                   "per_op": per_op, "autotuned": out["tuning"], "device_fault_flags": flags,
+                   "wall_s": round(wall, 3),
                    "setup_s": round(t_setup, 1)},
         "roofline": roofline,
         "cpu_baseline": None,
     }
     if not args.no_cpu:
+        print("[bench] per-range check: 64 batch ranges alone", file=sys.stderr, flush=True)
+        per_range = per_range_leg(host, out, dev)
+        flags |= per_range["status"]
         print("[bench] CPU leg: oracle (serial), oracle on every core, plain loops", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        errs, base = cpu_leg(host, out)
+        errs, base = cpu_leg(host, out, per_range)
         for name, e in errs.items():
             per_op[name]["error_vs_fp64_oracle"] = e
         base["leg_s"] = round(time.perf_counter() - t0, 1)
         line["cpu_baseline"] = base
+        line["config"]["device_fault_flags"] = flags
     print(json.dumps(line), flush=True)
+    if args.accuracy:
+        if args.no_cpu:
+            print("[bench] --accuracy needs the CPU leg: no record written", file=sys.stderr, flush=True)
+        else:
+            write_accuracy(args.accuracy, line, torch.cuda.get_device_name(dev))
     return 0 if flags == 0 else 1
 
 

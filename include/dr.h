@@ -186,12 +186,17 @@ typedef struct dr_table {
     int32_t reserved;   /* must be 0 */
 } dr_table;
 
-/* Launch shape. block_threads: 256 (the only shape built in this version);
- * items_per_thread: elements per thread per tile, one of the values
- * dr_tuning_supported accepts; flags: DR_TUNE_* bits. NULL = the built-in
- * default for the call: 16 items per thread, except bfloat16 reductions (32)
- * and the scan defaults described at dr_inclusive_scan. dr_plan and
- * dr_workspace_bytes given NULL assume the same defaults. */
+/* Launch shape. block_threads: threads per workgroup, 0 or 256 for every
+ * kernel; 512 and 1024 for the single-pass look-back scan only
+ * (DR_TUNE_TILE_PER_BLOCK; binary32 sums of the identity view with binary64
+ * carries, plain or fused with the compensated dot), any other call with
+ * them returns DR_ERR_UNSUPPORTED. items_per_thread: elements per thread per
+ * tile (a tile is block_threads * items_per_thread elements), one of the
+ * values dr_tuning_supported accepts; flags: DR_TUNE_* bits. NULL = the
+ * built-in default for the call: 256 threads, 16 items per thread, except
+ * bfloat16 reductions (32) and the scan defaults described at
+ * dr_inclusive_scan. dr_plan and dr_workspace_bytes given NULL assume the
+ * same defaults; given a tuning, they size for its tile. */
 typedef struct dr_tuning {
     int32_t block_threads;
     int32_t items_per_thread;
@@ -204,7 +209,12 @@ typedef struct dr_tuning {
  * workgroups each sum many tiles and combine once. For inclusive_scan /
  * scan_reduce: one kernel whose tiles, in block-index order, take their
  * carries from a decoupled look-back over their predecessors, instead of
- * the default read-only tile-totals pass followed by the apply pass. */
+ * the default read-only tile-totals pass followed by the apply pass (the
+ * input is read once). In BATCH mode a tile's look-back stops at its range's
+ * first tile, so ranges of one tile never wait. The carries of binary32 /
+ * binary64 scans are then sums of the predecessors in an order that depends
+ * on timing: results stay within the same error bound but need not repeat
+ * bit for bit from run to run (integer results are exact either way). */
 enum { DR_TUNE_TILE_PER_BLOCK = 1 };
 
 /* dr_tuning.flags for inclusive_scan, scan (sum) and scan_reduce: one pass
@@ -244,9 +254,12 @@ const char* dr_status_string(dr_status status);
 /* Detail of the last error returned on the calling thread ("" if none). */
 const char* dr_last_error(void);
 
-/* 1 if (algo, view, out_dtype, tuning) has a built kernel, else 0. For
- * DR_ALGO_REDUCE `out_dtype` carries the dr_acc instead; for
- * DR_ALGO_SCAN_REDUCE the reduce view is mul, compensated. */
+/* 1 if (algo, view, out_dtype, tuning) has a built kernel, else 0: the
+ * tuning's block_threads, items_per_thread and form flag (the look-back
+ * form has shapes of its own, see dr_tuning). For DR_ALGO_REDUCE
+ * `out_dtype` carries the dr_acc instead; for DR_ALGO_SCAN the carries are
+ * the default (binary64 for binary32 input); for DR_ALGO_SCAN_REDUCE the
+ * reduce view is mul, compensated. */
 int dr_tuning_supported(int32_t algo, const dr_view* view, int32_t out_dtype,
                         const dr_tuning* tuning);
 

@@ -1,7 +1,13 @@
-"""Tile-shape autotuner: picks items_per_thread (elements per thread per
-tile; 256 threads per workgroup) for a call by timing every shape the
-library has a kernel for, and caches the choice in a JSON file keyed by
-device, algorithm, dtype, op, mode and a size class.
+"""Launch-shape autotuner: picks the workgroup size (block_threads), the
+elements per thread per tile (items_per_thread) and, for scans, the form
+(reduce-then-scan or the single-pass look-back) of a call by timing every
+shape the library has a kernel for, and caches the choice in a JSON file
+keyed by device, algorithm, dtype, op, mode and a size class.
+
+Search space: block_threads in BLOCKS x items_per_thread in ITEMS x the
+scan forms in SCAN_FORMS, cut to what dr_tuning_supported accepts (the
+look-back scan is built at 256, 512 and 1024 threads; every other kernel
+at 256).
 
 Cache file: $DR_TUNE_CACHE, else ~/.cache/paper_2406_00158_amd/tune.json.
 The tuner never runs while a stream is being captured into a graph: tune
@@ -18,7 +24,9 @@ import torch
 
 from . import binding as B
 
-CANDIDATES = (16, 32, 64)
+BLOCKS = (256, 512, 1024)
+ITEMS = (4, 8, 16, 32, 64)
+SCAN_FORMS = (("two_pass", B.DR_TUNE_TWO_PASS), ("look_back", B.DR_TUNE_TILE_PER_BLOCK))
 _cache: dict | None = None
 
 
@@ -60,35 +68,60 @@ def key(algo: int, view: B.dr_view, out_dtype: int, table: B.Table, extra: str =
                      size_class(table.n_segments, table.total_length), extra])
 
 
-def supported(algo: int, view: B.dr_view, out_dtype: int) -> list[int]:
+def form_name(flags: int) -> str:
+    for name, f in SCAN_FORMS:
+        if flags == f:
+            return name
+    return "default" if flags == 0 else f"flags {flags}"
+
+
+def label(t: B.dr_tuning) -> str:
+    """`256x32/look_back`: block_threads x items_per_thread / form."""
+    return f"{t.block_threads}x{t.items_per_thread}/{form_name(t.flags)}"
+
+
+def candidates(algo: int, view: B.dr_view, out_dtype: int) -> list[B.dr_tuning]:
+    """Every (block_threads, items_per_thread, form) the library has a
+    kernel for, for this call."""
+    forms = SCAN_FORMS if algo in (B.DR_ALGO_SCAN, B.DR_ALGO_SCAN_REDUCE) else (("default", 0),)
     out = []
-    for items in CANDIDATES:
-        t = B.make_tuning(items)
-        if B.lib().dr_tuning_supported(algo, ctypes.byref(view), out_dtype, ctypes.byref(t)):
-            out.append(items)
+    for block in BLOCKS:
+        for items in ITEMS:
+            for _, fl in forms:
+                t = B.dr_tuning(block, items, fl, 0)
+                if B.lib().dr_tuning_supported(algo, ctypes.byref(view), out_dtype, ctypes.byref(t)):
+                    out.append(t)
     return out
+
+
+def _from_entry(e: dict) -> B.dr_tuning:
+    return B.dr_tuning(int(e.get("block_threads", 256)), int(e["items"]), int(e.get("flags", 0)), 0)
 
 
 def tune(algo: int, view: B.dr_view, out_dtype: int, table: B.Table, call, reps: int = 5,
          extra: str = "") -> B.dr_tuning | None:
     """Return the fastest tuning for `call(tuning)`, timing it on `table`'s
     device the first time this (algo, view, size class) is seen. `call`
-    must run the operation once with the given tuning."""
+    must run the operation once with the given tuning. The cache entry
+    (`entry(...)`) keeps every candidate's time."""
     k = key(algo, view, out_dtype, table, extra)
     cache = _load()
     if k in cache:
-        return B.make_tuning(cache[k]["items"])
+        return _from_entry(cache[k])
     if torch.cuda.is_current_stream_capturing():
         return None   # never time inside a capture: defaults apply
-    cands = supported(algo, view, out_dtype)
-    if len(cands) <= 1:
-        cache[k] = {"items": cands[0] if cands else 16, "ms": None}
+    cands = candidates(algo, view, out_dtype)
+    if not cands:
+        return None
+    if len(cands) == 1:
+        t = cands[0]
+        cache[k] = {"block_threads": t.block_threads, "items": t.items_per_thread, "flags": t.flags,
+                    "label": label(t), "ms": None}
         _save()
-        return B.make_tuning(cache[k]["items"])
+        return t
     stream = torch.cuda.current_stream(table.device)
     best, best_ms, results = None, float("inf"), {}
-    for items in cands:
-        tu = B.make_tuning(items)
+    for tu in cands:
         call(tu)   # warm-up (and plan)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -97,9 +130,15 @@ def tune(algo: int, view: B.dr_view, out_dtype: int, table: B.Table, call, reps:
         e1.record(stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        results[items] = ms
+        results[label(tu)] = ms
         if ms < best_ms:
-            best, best_ms = items, ms
-    cache[k] = {"items": best, "ms": best_ms, "all": {str(i): v for i, v in results.items()}}
+            best, best_ms = tu, ms
+    cache[k] = {"block_threads": best.block_threads, "items": best.items_per_thread, "flags": best.flags,
+                "label": label(best), "ms": best_ms, "all": results}
     _save()
-    return B.make_tuning(best)
+    return best
+
+
+def entry(algo: int, view: B.dr_view, out_dtype: int, table: B.Table, extra: str = "") -> dict | None:
+    """The cached choice (and every candidate's time) for this call, if tuned."""
+    return _load().get(key(algo, view, out_dtype, table, extra))

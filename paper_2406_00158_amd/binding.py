@@ -157,10 +157,11 @@ WS_ITEMS = {DR_F32: 32, DR_BF16: 32, DR_I32: 32, DR_F64: 16}
 WS_ITEMS_FUSED = 16
 
 
-def make_tuning(items_per_thread: int | None, flags: int = 0) -> dr_tuning | None:
-    if items_per_thread is None and not flags:
+def make_tuning(items_per_thread: int | None, flags: int = 0, block_threads: int = 256) -> dr_tuning | None:
+    """A launch shape; None (the library's defaults) when nothing is set."""
+    if items_per_thread is None and not flags and block_threads == 256:
         return None
-    return dr_tuning(256, int(items_per_thread or 0), int(flags), 0)
+    return dr_tuning(int(block_threads), int(items_per_thread or 0), int(flags), 0)
 
 
 # --- segment tables -----------------------------------------------------------

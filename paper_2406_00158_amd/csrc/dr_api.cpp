@@ -168,15 +168,24 @@ dr_status check_host_rows(const dr_table* t, int arity, int nout, int ies, int o
     return DR_OK;
 }
 
-dr_status resolve_items(const dr_tuning* tu, int algo, int in_dt, int& items) {
+// Items per thread and workgroup size of a call: the defaults, or the
+// tuning's. 512- and 1024-thread workgroups run the look-back scan only.
+dr_status resolve_shape(const dr_tuning* tu, int algo, int in_dt, int& items, int& block) {
     items = default_items(algo, in_dt);
+    block = kBlock;
     if (!tu) return DR_OK;
     const int32_t forms = DR_TUNE_TILE_PER_BLOCK | DR_TUNE_SPECIALIZED | DR_TUNE_TWO_PASS | DR_TUNE_CHAINED;
     if ((tu->flags & ~forms) || tu->reserved) return fail(DR_ERR_INVALID_ARG, "unknown tuning bits");
     const int32_t f = tu->flags & forms;
     if (f & (f - 1)) return fail(DR_ERR_INVALID_ARG, "at most one form flag (DR_TUNE_*) per call");
-    if (tu->block_threads != 0 && tu->block_threads != kBlock)
-        return fail(DR_ERR_UNSUPPORTED, "block_threads must be %d", kBlock);
+    if (tu->block_threads != 0 && tu->block_threads != kBlock) {
+        if (tu->block_threads != 512 && tu->block_threads != 1024)
+            return fail(DR_ERR_UNSUPPORTED, "block_threads must be 256, 512 or 1024");
+        if ((algo != DR_ALGO_SCAN && algo != DR_ALGO_SCAN_REDUCE) || f != DR_TUNE_TILE_PER_BLOCK)
+            return fail(DR_ERR_UNSUPPORTED, "block_threads %d: only the look-back scan (DR_TUNE_TILE_PER_BLOCK) "
+                                            "is built with more than %d threads", (int)tu->block_threads, kBlock);
+        block = tu->block_threads;
+    }
     if (tu->items_per_thread != 0) items = tu->items_per_thread;
     return DR_OK;
 }
@@ -228,6 +237,7 @@ WsLayout layout_for(int algo, int64_t m, int64_t tmax) {
 struct Prepared {
     LaunchArgs a;
     int64_t grid;
+    int block;   // threads per workgroup
 };
 
 dr_status prepare(const dr_table* t, int algo, int in_dt, int out_dt, int arity, int nout,
@@ -239,11 +249,12 @@ dr_status prepare(const dr_table* t, int algo, int in_dt, int out_dt, int arity,
     const int oes = nout > 0 ? dtype_size(out_dt) : 0;
     s = check_host_rows(t, arity, nout, ies, oes, inplace_ok);
     if (s) return s;
-    s = resolve_items(tu, algo, in_dt, items);
+    int block = kBlock;
+    s = resolve_shape(tu, algo, in_dt, items, block);
     if (s) return s;
     const int V = 16 / ies;
     if (items <= 0 || items % V != 0) return fail(DR_ERR_UNSUPPORTED, "items_per_thread %d", items);
-    const int64_t tile = (int64_t)kBlock * items;
+    const int64_t tile = (int64_t)block * items;
     const int64_t tmax = tmax_for(t->n_segments, t->total_length, tile, ies);
     if (tmax >= ((int64_t)1 << 31)) return fail(DR_ERR_UNSUPPORTED, "too many tiles (%lld)", (long long)tmax);
     const WsLayout lay = layout_for(algo, t->n_segments, tmax);
@@ -271,6 +282,7 @@ dr_status prepare(const dr_table* t, int algo, int in_dt, int out_dt, int arity,
     a.lay = lay;
     a.spin_ticks = spin_ticks();
     p.grid = tmax;
+    p.block = block;
     return DR_OK;
 }
 
@@ -314,6 +326,23 @@ dr_status launch(LaunchFn fn, Prepared& p, void* stream, const char* what) {
     return ok();
 }
 
+// The sum-scan kernel of a call: the 256-thread kernels (every form) at the
+// usual tiles, else a shape built for the look-back form only
+// (k_scan_wide.hip), which the call must have asked for.
+LaunchFn scan_kernel(int in, int out, int op, bool c64, int items, int block, const dr_tuning* tu) {
+    if (block == kBlock)
+        if (LaunchFn f = find_scan(in, out, op, c64, items)) return f;
+    const bool tpb = tu && (tu->flags & DR_TUNE_TILE_PER_BLOCK);
+    return tpb ? find_scan_wide(in, out, op, c64, false, 0, items, block) : nullptr;
+}
+
+LaunchFn scan_reduce_kernel(int in, int rop, int acc, int items, int block, const dr_tuning* tu) {
+    if (block == kBlock)
+        if (LaunchFn f = find_scan_reduce(in, rop, acc, items)) return f;
+    const bool tpb = tu && (tu->flags & DR_TUNE_TILE_PER_BLOCK);
+    return tpb && rop == DR_OP_MUL ? find_scan_wide(in, in, DR_OP_IDENTITY, true, true, acc, items, block) : nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -337,15 +366,16 @@ const char* dr_last_error(void) { return g_err.c_str(); }
 
 int dr_tuning_supported(int32_t algo, const dr_view* v, int32_t out_dtype, const dr_tuning* tu) {
     if (!v) return 0;
-    int items = 0;
-    if (resolve_items(tu, algo, v->in_dtype, items) != DR_OK) return 0;
+    int items = 0, block = kBlock;
+    if (resolve_shape(tu, algo, v->in_dtype, items, block) != DR_OK) return 0;
     switch (algo) {
     case DR_ALGO_FOR_EACH: return find_for_each(v->in_dtype, out_dtype, v->op, items) != nullptr;
     case DR_ALGO_REDUCE:
         return find_reduce(v->in_dtype, v->op, out_dtype /* acc */, items) != nullptr;
     case DR_ALGO_SCAN:
-        return find_scan(v->in_dtype, out_dtype, v->op, true, items) != nullptr;
-    case DR_ALGO_SCAN_REDUCE: return find_scan_reduce(v->in_dtype, DR_OP_MUL, DR_ACC_COMPENSATED, items) != nullptr;
+        return scan_kernel(v->in_dtype, out_dtype, v->op, true, items, block, tu) != nullptr;
+    case DR_ALGO_SCAN_REDUCE:
+        return scan_reduce_kernel(v->in_dtype, DR_OP_MUL, DR_ACC_COMPENSATED, items, block, tu) != nullptr;
     case DR_ALGO_BROADCAST_MUL: return find_broadcast_mul(v->in_dtype, v->op, items) != nullptr;
     default: return 0;
     }
@@ -359,11 +389,11 @@ dr_status dr_workspace_bytes(int32_t algo, int64_t n_segments, int64_t total_len
     if (n_segments < 0 || total_length < 0) return fail(DR_ERR_INVALID_ARG, "negative size");
     const int ies = dtype_size(view->in_dtype);
     if (ies == 0) return fail(DR_ERR_UNSUPPORTED, "input dtype %d", (int)view->in_dtype);
-    int items = 0;
-    dr_status s = resolve_items(tuning, algo, view->in_dtype, items);
+    int items = 0, block = kBlock;
+    dr_status s = resolve_shape(tuning, algo, view->in_dtype, items, block);
     if (s) return s;
     if (items <= 0 || items % (16 / ies)) return fail(DR_ERR_UNSUPPORTED, "items_per_thread %d", items);
-    const int64_t tmax = tmax_for(n_segments, total_length, (int64_t)kBlock * items, ies);
+    const int64_t tmax = tmax_for(n_segments, total_length, (int64_t)block * items, ies);
     *bytes = (size_t)layout_for(algo, n_segments, tmax).bytes;
     return ok();
 }
@@ -545,7 +575,7 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
                 ws_on ? wsu : scan_tuning(table, in, out_dtype, view->op, tuning, dflt), ws, ws_bytes, true,
                 view->op == DR_OP_IDENTITY, p, items);
     if (s) return s;
-    LaunchFn fn = find_scan(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items);
+    LaunchFn fn = scan_kernel(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items, p.block, tuning);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
     p.a.alpha = view->alpha;
     p.a.flags = flags;
@@ -633,7 +663,7 @@ dr_status dr_scan(const dr_table* table, const dr_view* view, int32_t out_dtype,
                 true, view->op == DR_OP_IDENTITY, p, items);
     if (s) return s;
     LaunchFn fn = mm ? find_scan_minmax(in, out_dtype)
-                     : find_scan(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items);
+                     : scan_kernel(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items, p.block, tuning);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
     p.a.alpha = view->alpha;
     p.a.flags = flags;
@@ -677,7 +707,7 @@ dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view, const 
     if (s) return s;
     s = prepare(table, DR_ALGO_SCAN_REDUCE, in, in, 2, 1, ws_on ? wsu : tuning, ws, ws_bytes, true, true, p, items);
     if (s) return s;
-    LaunchFn fn = find_scan_reduce(in, reduce_view->op, acc, items);
+    LaunchFn fn = scan_reduce_kernel(in, reduce_view->op, acc, items, p.block, tuning);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "fused scan kernel not built for this combination");
     p.a.flags = flags;
     if (ws_on) p.a.flags |= kFlagSpecialized;

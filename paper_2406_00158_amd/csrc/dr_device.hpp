@@ -686,19 +686,19 @@ template <int DT> __device__ __forceinline__ typename elem<DT>::T zero_elem() {
 // row is 16-byte aligned there: all accesses are whole 16-byte vectors with
 // no bounds checks (the common case; only a segment's first and last tiles,
 // and misaligned rows, take the checked path).
-template <int V, int SLOTS>
+template <int V, int SLOTS, int BLOCK = kBlock>
 __device__ __forceinline__ bool tile_full(const SegInfo& si, int64_t u0) {
-    constexpr int64_t TILE = (int64_t)kBlock * SLOTS * V;
+    constexpr int64_t TILE = (int64_t)BLOCK * SLOTS * V;
     const int64_t j0 = u0 - si.shift;
     return si.vec_ok && j0 >= 0 && j0 + TILE <= si.n;
 }
 
 // The slots of a full tile (tile_full): whole vectors, no checks.
-template <int DT, int SLOTS, int V = vwidth<DT>(), bool NT = true>
+template <int DT, int SLOTS, int V = vwidth<DT>(), bool NT = true, int BLOCK = kBlock>
 __device__ __forceinline__ void load_slots_full(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
                                                 int64_t u0, int w, int l, bool rev) {
     using R = typename vbits<V * esize<DT>()>::T;
-    constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+    constexpr int64_t NV = (int64_t)BLOCK * SLOTS;
     const int64_t p0 = (int64_t)(w * SLOTS) * 64 + l;
     const int64_t q0 = rev ? (NV - 1 - p0) : p0;
     const char* b = (const char*)base + (u0 - si.shift + q0 * V) * esize<DT>();
@@ -712,10 +712,10 @@ __device__ __forceinline__ void load_slots_full(vec<DT, V> (&x)[SLOTS], const vo
 
 // The slots of any tile, each element checked against the segment (the
 // elements outside it read as 0).
-template <int DT, int SLOTS, int V = vwidth<DT>(), bool NT = true>
+template <int DT, int SLOTS, int V = vwidth<DT>(), bool NT = true, int BLOCK = kBlock>
 __device__ __forceinline__ void load_slots_checked(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
                                                    int64_t u0, int w, int l, bool rev) {
-    constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+    constexpr int64_t NV = (int64_t)BLOCK * SLOTS;
     const int64_t p0 = (int64_t)(w * SLOTS) * 64 + l;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -736,25 +736,25 @@ __device__ __forceinline__ void load_slots_checked(vec<DT, V> (&x)[SLOTS], const
     }
 }
 
-template <int DT, int SLOTS, int V = vwidth<DT>(), bool NT = true>
+template <int DT, int SLOTS, int V = vwidth<DT>(), bool NT = true, int BLOCK = kBlock>
 __device__ __forceinline__ void load_slots(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
                                            int64_t u0, int w, int l, bool rev) {
-    if (tile_full<V, SLOTS>(si, u0)) load_slots_full<DT, SLOTS, V, NT>(x, base, si, u0, w, l, rev);
-    else load_slots_checked<DT, SLOTS, V, NT>(x, base, si, u0, w, l, rev);
+    if (tile_full<V, SLOTS, BLOCK>(si, u0)) load_slots_full<DT, SLOTS, V, NT, BLOCK>(x, base, si, u0, w, l, rev);
+    else load_slots_checked<DT, SLOTS, V, NT, BLOCK>(x, base, si, u0, w, l, rev);
 }
 
 // The two inputs of a zipped view (y only when ZIP) under one branch on
 // tile_full, so that a full tile issues both inputs' loads before any wait
 // (see load_slots_k).
-template <bool ZIP, int DT, int SLOTS, int V = vwidth<DT>()>
+template <bool ZIP, int DT, int SLOTS, int V = vwidth<DT>(), int BLOCK = kBlock>
 __device__ __forceinline__ void load_pair(vec<DT, V> (&x)[SLOTS], vec<DT, V> (&y)[SLOTS], const SegInfo& si,
                                           int64_t u0, int w, int l, bool rev) {
-    if (tile_full<V, SLOTS>(si, u0)) {
-        load_slots_full<DT, SLOTS, V>(x, si.in0, si, u0, w, l, rev);
-        if constexpr (ZIP) load_slots_full<DT, SLOTS, V>(y, si.in1, si, u0, w, l, rev);
+    if (tile_full<V, SLOTS, BLOCK>(si, u0)) {
+        load_slots_full<DT, SLOTS, V, true, BLOCK>(x, si.in0, si, u0, w, l, rev);
+        if constexpr (ZIP) load_slots_full<DT, SLOTS, V, true, BLOCK>(y, si.in1, si, u0, w, l, rev);
     } else {
-        load_slots_checked<DT, SLOTS, V>(x, si.in0, si, u0, w, l, rev);
-        if constexpr (ZIP) load_slots_checked<DT, SLOTS, V>(y, si.in1, si, u0, w, l, rev);
+        load_slots_checked<DT, SLOTS, V, true, BLOCK>(x, si.in0, si, u0, w, l, rev);
+        if constexpr (ZIP) load_slots_checked<DT, SLOTS, V, true, BLOCK>(y, si.in1, si, u0, w, l, rev);
     }
 }
 
@@ -764,19 +764,19 @@ __device__ __forceinline__ void load_pair(vec<DT, V> (&x)[SLOTS], vec<DT, V> (&y
 // branch inside each call, the compiler joins the unchecked loads of one
 // input with the checked ones before the next input's, and that join waits
 // for every load in flight: the vector memory counter is in order).
-template <bool FULL, int DT, int SLOTS, int V = vwidth<DT>()>
+template <bool FULL, int DT, int SLOTS, int V = vwidth<DT>(), int BLOCK = kBlock>
 __device__ __forceinline__ void load_slots_k(vec<DT, V> (&x)[SLOTS], const void* base, const SegInfo& si,
                                              int64_t u0, int w, int l, bool rev) {
-    if constexpr (FULL) load_slots_full<DT, SLOTS, V>(x, base, si, u0, w, l, rev);
-    else load_slots<DT, SLOTS, V>(x, base, si, u0, w, l, rev);
+    if constexpr (FULL) load_slots_full<DT, SLOTS, V, true, BLOCK>(x, base, si, u0, w, l, rev);
+    else load_slots<DT, SLOTS, V, true, BLOCK>(x, base, si, u0, w, l, rev);
 }
 
 // Whether element e (memory order) of slot s of lane l of wave w lies
 // inside the segment; the loads fill the others with 0, which only a sum may
 // combine.
-template <int V, int SLOTS>
+template <int V, int SLOTS, int BLOCK = kBlock>
 __device__ __forceinline__ bool elem_in(const SegInfo& si, int64_t u0, int w, int l, int s, int e, bool rev) {
-    constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+    constexpr int64_t NV = (int64_t)BLOCK * SLOTS;
     const int64_t p = (int64_t)(w * SLOTS + s) * 64 + l;
     const int64_t q = rev ? (NV - 1 - p) : p;
     const int64_t j = u0 + q * V - si.shift + e;
@@ -785,10 +785,10 @@ __device__ __forceinline__ bool elem_in(const SegInfo& si, int64_t u0, int w, in
 
 // Store the V outputs of slot s (given in memory order). `full` is
 // tile_full() of the tile.
-template <class OT, int V, int SLOTS>
+template <class OT, int V, int SLOTS, int BLOCK = kBlock>
 __device__ __forceinline__ void store_slot(void* base, const SegInfo& si, int64_t u0, int w, int l,
                                            int s, bool rev, bool full, const OT (&o)[V]) {
-    constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+    constexpr int64_t NV = (int64_t)BLOCK * SLOTS;
     const int64_t p = (int64_t)(w * SLOTS + s) * 64 + l;
     const int64_t q = rev ? (NV - 1 - p) : p;
     const int64_t j = u0 + q * V - si.shift;
@@ -806,16 +806,16 @@ __device__ __forceinline__ void store_slot(void* base, const SegInfo& si, int64_
 // store_slot with the tile's fullness known at compile time: a full tile
 // (whole in its segment, rows aligned) stores each slot as one unchecked
 // vector, so the kernel branches once per tile rather than once per slot.
-template <bool FULL, class OT, int V, int SLOTS>
+template <bool FULL, class OT, int V, int SLOTS, int BLOCK = kBlock>
 __device__ __forceinline__ void store_slot_k(void* base, const SegInfo& si, int64_t u0, int w, int l, int s,
                                              bool rev, const OT (&o)[V]) {
     if constexpr (FULL) {
-        constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+        constexpr int64_t NV = (int64_t)BLOCK * SLOTS;
         const int64_t p = (int64_t)(w * SLOTS + s) * 64 + l;
         const int64_t q = rev ? (NV - 1 - p) : p;
         store_run<OT, V>(base, u0 + q * V - si.shift, o);
     } else {
-        store_slot<OT, V, SLOTS>(base, si, u0, w, l, s, rev, false, o);
+        store_slot<OT, V, SLOTS, BLOCK>(base, si, u0, w, l, s, rev, false, o);
     }
 }
 

@@ -124,6 +124,10 @@ LaunchFn find_reduce_minmax(int in_dt, int op, int items);
 LaunchFn find_scan_minmax(int in_dt, int out_dt);
 LaunchFn find_scan(int in_dt, int out_dt, int op, bool carry64, int items);
 LaunchFn find_scan_reduce(int in_dt, int reduce_op, int acc, int items);
+// The look-back scan at the shapes k_scan.hip does not build (512 / 1024
+// threads, or 4 / 8 items per thread): binary32 sums with binary64 carries,
+// plain (fused = false) or fused with the compensated dot.
+LaunchFn find_scan_wide(int in_dt, int out_dt, int op, bool carry64, bool fused, int acc, int items, int block);
 LaunchFn find_broadcast_mul(int in_dt, int op, int items);
 LaunchFn find_black_scholes(int items);
 hipError_t launch_plan(const LaunchArgs& a, hipStream_t stream);     // prefix + tile -> segment map

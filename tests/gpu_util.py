@@ -86,32 +86,35 @@ def gather(segs) -> np.ndarray:
 
 # --- error bounds -------------------------------------------------------------
 
-def scan_depth(items: int = ITEMS, elem_bytes: int = 4) -> int:
+def scan_depth(items: int = ITEMS, elem_bytes: int = 4, block: int = BLOCK) -> int:
     """Most roundings an element's tile-local binary32 prefix goes through:
     the serial scan of one 16-byte vector, the six-step wave scan, the
     running offsets of the thread's earlier vectors and of the earlier
-    waves, and two joins."""
+    waves (block / 64 of them), and two joins."""
     V = 16 // elem_bytes
     slots = items // V
-    return (V - 1) + 6 + slots + BLOCK // 64 + 2
+    return (V - 1) + 6 + slots + block // 64 + 2
 
 
 def scan_fp32_bound(ref: np.ndarray, absprefix: np.ndarray, items: int = ITEMS, elem_bytes: int = 4,
-                    tiles: int = 1) -> np.ndarray:
+                    tiles: int = 1, block: int = BLOCK) -> np.ndarray:
     """|y - y_ref| bound of a binary32 scan with binary64 carries: one final
     rounding to binary32, the tile-local binary32 roundings, and the
-    binary64 carry chain."""
-    d = scan_depth(items, elem_bytes)
+    binary64 carry chain (a sum of at most `tiles` tile totals, in any
+    order)."""
+    d = scan_depth(items, elem_bytes, block)
     return U32 * np.abs(ref) + d * U32 * absprefix + (tiles + 2) * U64 * absprefix
 
 
-def reduce_bound(absum: float, acc: str, items: int = ITEMS, in_bytes: int = 4, tiles: int = 1) -> float:
+def reduce_bound(absum: float, acc: str, items: int = ITEMS, in_bytes: int = 4, tiles: int = 1,
+                 block: int = BLOCK) -> float:
     """|R - R_ref| bound of a reduction of `tiles` tiles of 256 * `items`
     elements. binary32 / bfloat16 inputs accumulate in binary32 through the
     workgroup: each thread runs serially over its elements (its tile's
     `items`, or in the streaming form those of every tile its workgroup
     takes: at most ceil(tiles / 256) tiles, the device running at least one
-    workgroup per CU), then a 64-lane tree and the 4 waves in order; plain:
+    workgroup per CU), then a 64-lane tree and the block / 64 waves in
+    order; plain:
     recursive summation, (n + 10) u32 sum|v|; compensated: TwoSum/TwoProduct
     pairs leave only second-order terms, 4 ((n + 10) u32)^2 sum|v| (Ogita,
     Rump and Oishi's Sum2 / Dot2). The workgroup partials are widened and
@@ -119,8 +122,8 @@ def reduce_bound(absum: float, acc: str, items: int = ITEMS, in_bytes: int = 4, 
     per_thread = items * max(1, -(-tiles // 256))
     b64 = (2 * np.log2(max(tiles, 2)) + 8) * U64 * absum
     if in_bytes == 8:
-        return (per_thread + 10) * U64 * absum + b64
-    depth = per_thread + 10
+        return (per_thread + 6 + block // 64) * U64 * absum + b64
+    depth = per_thread + 6 + block // 64
     if acc == "plain":
         return depth * U32 * absum + b64
     return 4 * (depth * U32) ** 2 * absum + b64

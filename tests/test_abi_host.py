@@ -234,3 +234,46 @@ def test_generic_operator_argument_errors():
     assert L.dr_reduce(ctypes.byref(tr), ctypes.byref(v), B.DR_COMBINE_MIN, 0, None, O, 0x40000000, 1 << 30,
                        ctypes.byref(B.make_tuning(32)), None) == -2
     del keep, keep2
+
+
+def test_wide_look_back_shapes():
+    """512- and 1024-thread workgroups (and 4 / 8 items at 256) exist for the
+    look-back scan only: binary32 sums with binary64 carries, plain or fused
+    with the compensated dot. Everything else with them is refused on the
+    host, and workspace sizes follow the tile of block_threads x items."""
+    L = B.lib()
+    vid, vmul = B.make_view("identity", B.DR_F32), B.make_view("mul", B.DR_F32)
+    sup = lambda algo, v, odt, tu: L.dr_tuning_supported(algo, ctypes.byref(v), odt, ctypes.byref(tu))
+    lb = B.DR_TUNE_TILE_PER_BLOCK
+    for block, items in ((512, 8), (512, 16), (512, 32), (1024, 4), (1024, 8), (1024, 16), (256, 4), (256, 8)):
+        tu = B.make_tuning(items, lb, block)
+        assert sup(B.DR_ALGO_SCAN, vid, B.DR_F32, tu) == 1, (block, items)
+        assert sup(B.DR_ALGO_SCAN_REDUCE, vid, B.DR_F32, tu) == 1, (block, items)
+        # the same shape in the two-pass form, for other dtypes or algorithms: not built
+        assert sup(B.DR_ALGO_SCAN, vid, B.DR_F32, B.make_tuning(items, B.DR_TUNE_TWO_PASS, block)) == 0
+        assert sup(B.DR_ALGO_SCAN, B.make_view("identity", B.DR_I32), B.DR_I64, tu) == 0
+    assert sup(B.DR_ALGO_SCAN, vid, B.DR_F32, B.make_tuning(32, lb, 1024)) == 0   # 128 registers per thread
+    assert sup(B.DR_ALGO_REDUCE, vmul, B.DR_ACC_COMPENSATED, B.make_tuning(16, 0, 512)) == 0
+    assert sup(B.DR_ALGO_FOR_EACH, vid, B.DR_F32, B.make_tuning(16, 0, 512)) == 0
+    assert sup(B.DR_ALGO_SCAN, vid, B.DR_F32, B.make_tuning(16, lb, 384)) == 0
+    # tile = block x items: 2^28 elements at 512 x 16 need the tile words of 256 x 32
+    size = ctypes.c_size_t(0)
+    sizes = []
+    for block, items in ((512, 16), (256, 32), (256, 16)):
+        tu = B.make_tuning(items, lb, block)
+        assert L.dr_workspace_bytes(B.DR_ALGO_SCAN, 16, 1 << 28, ctypes.byref(vid), ctypes.byref(tu),
+                                    ctypes.byref(size)) == 0
+        sizes.append(size.value)
+    assert sizes[0] == sizes[1] < sizes[2]
+    # calls: the wide shape in the two-pass form, and a reduction at 512 threads, fail before any launch
+    t, keep = _host_table([((A,), (O,), 10)], 10)
+    tu = B.make_tuning(16, B.DR_TUNE_TWO_PASS, 512)
+    assert L.dr_inclusive_scan(ctypes.byref(t), ctypes.byref(vid), B.DR_F32, 0, 0x40000000, 1 << 30,
+                               ctypes.byref(tu), None) == B.DR_ERR_UNSUPPORTED
+    assert b"look-back" in L.dr_last_error()
+    tr, keep2 = _host_table([((A, Bp), (), 10)], 10)
+    init = ctypes.c_double(0.0)
+    tu = B.make_tuning(16, 0, 1024)
+    assert L.dr_transform_reduce(ctypes.byref(tr), ctypes.byref(vmul), 1, ctypes.byref(init), O, 0x40000000,
+                                 1 << 20, ctypes.byref(tu), None) == B.DR_ERR_UNSUPPORTED
+    del keep, keep2

@@ -112,11 +112,15 @@ def test_autotuner_picks_and_caches(tmp_path, monkeypatch):
     ws = B.Workspace(dev())
     view = B.make_view("identity", B.DR_F32)
     tu = AT.tune(B.DR_ALGO_SCAN_REDUCE, view, B.DR_F32, tab, lambda t: _run(tab, res, ws, t))
-    assert tu is not None and tu.items_per_thread in AT.CANDIDATES
+    assert tu is not None and tu.items_per_thread in AT.ITEMS and tu.block_threads in AT.BLOCKS
+    assert tu.flags in [f for _, f in AT.SCAN_FORMS]
+    e = AT.entry(B.DR_ALGO_SCAN_REDUCE, view, B.DR_F32, tab)
+    assert e["label"] == AT.label(tu) and len(e["all"]) == len(AT.candidates(B.DR_ALGO_SCAN_REDUCE, view, B.DR_F32))
+    assert {AT.form_name(f) for _, f in AT.SCAN_FORMS} <= {k.split("/")[1] for k in e["all"]}
     assert os.path.exists(tmp_path / "tune.json")
     AT._cache = None
     tu2 = AT.tune(B.DR_ALGO_SCAN_REDUCE, view, B.DR_F32, tab, lambda t: pytest.fail("re-timed a cached shape"))
-    assert tu2.items_per_thread == tu.items_per_thread
+    assert (tu2.block_threads, tu2.items_per_thread, tu2.flags) == (tu.block_threads, tu.items_per_thread, tu.flags)
     _run(tab, res, ws, tu)
     want, mag = O.reduce(I.split(xs, lengths), I.split(ys, lengths), O.F32, O.MUL, mode=O.BATCH)
     assert np.all(np.abs(dev_to_np(res) - want) <= reduce_bound(mag, "compensated", items=64, tiles=64))
