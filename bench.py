@@ -768,6 +768,23 @@ def configs_report(reps: int) -> int:
     with torch.cuda.graph(g):
         fused()
     report("C5 batch", "fused scan + dot, hipGraph replay", 12 * n5, g.replay)
+    # the autotuner's shape (as in the bench step), eager and from a graph
+    from paper_2406_00158_amd import autotune as AT
+    tu = AT.tune(B.DR_ALGO_SCAN_REDUCE, vid, B.DR_F32, tab, lambda t_: B.dr_scan_reduce(
+        tab, vid, vmul, B.DR_ACC_COMPENSATED, 0.0, r5, workspace=ws5, host_check=False, tuning=t_))
+    fused_t = lambda: B.dr_scan_reduce(tab, vid, vmul, B.DR_ACC_COMPENSATED, 0.0, r5, workspace=ws5,
+                                       host_check=False, tuning=tu)
+    report("C5 batch", f"fused scan + dot, autotuned {AT.label(tu)}, eager", 12 * n5, fused_t)
+    fused_t()
+    torch.cuda.synchronize()
+    gt = torch.cuda.CUDAGraph()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fused_t()
+    torch.cuda.current_stream().wait_stream(side)
+    with torch.cuda.graph(gt):
+        fused_t()
+    report("C5 batch", f"fused scan + dot, autotuned {AT.label(tu)}, hipGraph replay", 12 * n5, gt.replay)
     ws_s, ws_d, ws_b, ws_r = (B.Workspace(dev) for _ in range(4))
     report("C5 batch", "unfused: scan, then dot (two calls)", 16 * n5, lambda: (
         B.dr_inclusive_scan(tsc, vid, B.DR_F32, workspace=ws_s, host_check=False),
@@ -780,6 +797,11 @@ def configs_report(reps: int) -> int:
         tbm, vmul, gg, 2, workspace=ws_b, host_check=False))
     report("C5 batch", "backward: scan adjoint (reverse scan)", 8 * n5, lambda: B.dr_inclusive_scan(
         trs, vid, B.DR_F32, B.DR_SCAN_REVERSE, workspace=ws_r, host_check=False))
+    tr = AT.tune(B.DR_ALGO_SCAN, vid, B.DR_F32, trs, lambda t_: B.dr_inclusive_scan(
+        trs, vid, B.DR_F32, B.DR_SCAN_REVERSE, workspace=ws_r, host_check=False, tuning=t_), extra="reverse")
+    report("C5 batch", f"backward: scan adjoint (reverse scan), autotuned {AT.label(tr)}", 8 * n5,
+           lambda: B.dr_inclusive_scan(trs, vid, B.DR_F32, B.DR_SCAN_REVERSE, workspace=ws_r, host_check=False,
+                                       tuning=tr))
     per = [(B.segments([[xs], [ys]], [[ss]]), r5[i:i + 1]) for i, (xs, ys, ss) in
            enumerate(zip(pieces(x, L), pieces(y, L), pieces(s5, L)))]
     ws1 = B.Workspace(dev)

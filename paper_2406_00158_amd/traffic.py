@@ -1,13 +1,19 @@
-"""HBM traffic per kernel launch from rocprofv3 hardware counters.
+"""Summaries of rocprofv3 runs: HBM traffic per kernel launch from the
+hardware counters, and kernel durations from a kernel trace.
 
-Two counter runs of the benchmark (FETCH_SIZE, then WRITE_SIZE; KiB per
-dispatch) are scaled by what the same counters read for a plain copy kernel
-of known size (`bench.py --copy-only`: a for_each identity over 2^28
+Traffic: two counter runs of the benchmark (FETCH_SIZE, then WRITE_SIZE;
+KiB per dispatch) are scaled by what the same counters read for a plain copy
+kernel of known size (`bench.py --copy-only`: a for_each identity over 2^28
 binary32 elements, 1 GiB read and 1 GiB written per launch), and written to
 profiles/traffic.json together with a hash of the kernel sources (bench.py
 reports the figure only while the sources are unchanged) and a text summary.
 
     python -m paper_2406_00158_amd.traffic FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR [OUT_MD]
+
+Durations: the `--stats` table of a `rocprofv3 --kernel-trace --stats
+--output-format csv` run, the library's kernels only, as a markdown table.
+
+    python -m paper_2406_00158_amd.traffic --kernels TRACE_DIR [OUT_MD]
 """
 from __future__ import annotations
 
@@ -87,7 +93,40 @@ def summarize(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_di
             "kernels": kernels}
 
 
+def kernel_stats(trace_dir: str) -> list[dict]:
+    """Rows of the kernel statistics CSV of a trace run (library kernels
+    first by total time, then the rest), durations in microseconds."""
+    rows = []
+    for f in glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append({"kernel": short_name(r["Name"]), "calls": int(r["Calls"]),
+                             "total_us": float(r["TotalDurationNs"]) / 1e3, "avg_us": float(r["AverageNs"]) / 1e3,
+                             "min_us": float(r["MinNs"]) / 1e3, "max_us": float(r["MaxNs"]) / 1e3})
+    rows.sort(key=lambda r: (not r["kernel"].startswith("k_"), -r["total_us"]))
+    return rows
+
+
+def kernels_md(trace_dir: str) -> str:
+    lines = ["| kernel | calls | total us | avg us | min us | max us |", "|---|---|---|---|---|---|"]
+    for r in kernel_stats(trace_dir):
+        if r["kernel"].startswith("k_"):
+            lines.append(f"| `{r['kernel']}` | {r['calls']} | {r['total_us']:.1f} | {r['avg_us']:.1f} | "
+                         f"{r['min_us']:.1f} | {r['max_us']:.1f} |")
+    return "\n".join(lines) + "\n"
+
+
 def main(argv: list[str]) -> int:
+    if argv and argv[0] == "--kernels":
+        if len(argv) < 2:
+            print(__doc__, file=sys.stderr)
+            return 2
+        text = kernels_md(argv[1])
+        print(text)
+        if len(argv) > 2:
+            with open(argv[2], "w") as f:
+                f.write(text)
+        return 0
     if len(argv) < 4:
         print(__doc__, file=sys.stderr)
         return 2
