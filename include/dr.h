@@ -239,10 +239,19 @@ enum { DR_TUNE_SPECIALIZED = 2 };
  * min scans always run this form. */
 enum { DR_TUNE_TWO_PASS = 4 };
 
-/* dr_tuning.flags, reserved for a chained single pass (chunks claimed from
- * a counter, each read once to publish its total and again from the L2
- * cache to be scanned and written). Switched off in this build: calls that
- * set it return DR_ERR_UNSUPPORTED. */
+/* dr_tuning.flags for inclusive_scan and scan (sums): the chained single
+ * pass. Workgroups claim chunks of 4 tiles from a counter; each chunk is
+ * read once from HBM to publish its total (its lines stay in the L2 cache)
+ * and read again from L2 one chunk later, when its carry is known, to be
+ * scanned and written. Carries are sums over a fixed shape (chunk totals
+ * folded per superblock of 128 chunks, running carries chained across
+ * superblocks), so results repeat from run to run. Built for one range
+ * (CONCAT) of sums of the identity view: F32 -> F32 (binary64 carries, or
+ * binary32 with DR_SCAN_CARRY_F32), I32 -> I64 and I32 -> I32, at 16 items
+ * per thread (items_per_thread 0 or 16), forward and reverse, with the
+ * initial value and the exclusive form of dr_scan. Any other call with it
+ * (BATCH tables, other dtypes or views, max / min, the fused scan_reduce)
+ * returns DR_ERR_UNSUPPORTED before anything is enqueued. */
 enum { DR_TUNE_CHAINED = 8 };
 
 /* Library version (DR_ABI_VERSION). Never fails. */
@@ -326,9 +335,10 @@ dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_
  * (reads the input again, writes the output once); carries are sums in a
  * fixed order, so results repeat from run to run (DR_TUNE_TWO_PASS names
  * this form explicitly). DR_TUNE_TILE_PER_BLOCK selects one kernel whose
- * tiles take their carries from a decoupled look-back, and
- * DR_TUNE_SPECIALIZED the single pass with specialised waves; at most one
- * form flag. Without a tuning, int32 scans of at most 2^22 elements take the
+ * tiles take their carries from a decoupled look-back, DR_TUNE_SPECIALIZED
+ * the single pass with specialised waves, and DR_TUNE_CHAINED the chained
+ * single pass (one range; the input read from HBM once); at most one form
+ * flag. Without a tuning, int32 scans of at most 2^22 elements take the
  * look-back form (lower latency, exact either way), and larger int32 ->
  * int64 scans of the identity view over tables of at most DR_SMALL_TABLE
  * rows use tiles of 64 items per thread (the output is twice the input's

@@ -19,8 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdr.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["dr_api.cpp", "k_elementwise.hip", "k_reduce.hip", "k_scan.hip", "k_scan_wide.hip", "k_plan.hip",
-           "dr_static.hip"]
+SOURCES = ["dr_api.cpp", "k_elementwise.hip", "k_reduce.hip", "k_scan.hip", "k_scan_wide.hip", "k_scan_chain.hip",
+           "k_plan.hip", "dr_static.hip"]
 HEADERS = ["dr_device.hpp", "dr_internal.hpp", "dr_combine.hpp", "k_scan_core.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -373,8 +373,11 @@ int dr_tuning_supported(int32_t algo, const dr_view* v, int32_t out_dtype, const
     case DR_ALGO_REDUCE:
         return find_reduce(v->in_dtype, v->op, out_dtype /* acc */, items) != nullptr;
     case DR_ALGO_SCAN:
+        if (tu && (tu->flags & DR_TUNE_CHAINED))
+            return block == kBlock && find_scan_chain(v->in_dtype, out_dtype, v->op, true, items) != nullptr;
         return scan_kernel(v->in_dtype, out_dtype, v->op, true, items, block, tu) != nullptr;
     case DR_ALGO_SCAN_REDUCE:
+        if (tu && (tu->flags & DR_TUNE_CHAINED)) return 0;
         return scan_reduce_kernel(v->in_dtype, DR_OP_MUL, DR_ACC_COMPENSATED, items, block, tu) != nullptr;
     case DR_ALGO_BROADCAST_MUL: return find_broadcast_mul(v->in_dtype, v->op, items) != nullptr;
     default: return 0;
@@ -476,8 +479,9 @@ dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_
 // Default form of an integer sum scan (no tuning given): up to 2^22
 // elements one kernel with a decoupled look-back has the lower latency (two
 // launches instead of three, about 11 us against 14 us); integer carries are
-// exact either way. Floating-point scans keep the two-pass form at every
-// size: its carries are sums in a fixed order, so results repeat exactly.
+// exact either way. Floating-point scans never take the look-back by
+// default: its carries depend on timing, while the two passes' and the
+// chained pass's are sums in a fixed order, so results repeat exactly.
 static bool prefer_single_pass(const dr_table* t, int in_dt, const dr_tuning* tu) {
     return !tu && in_dt == DR_I32 && t && t->total_length <= ((int64_t)1 << 22);
 }
@@ -492,11 +496,38 @@ static uint32_t sum_scan_form(const dr_table* t, int in_dt, const dr_tuning* tu)
     return 0u;
 }
 
-// The chained single pass is switched off: a GPU run of it (int32 -> int64,
-// reverse, 2^25 elements) faulted and the cause has not been found.
-static dr_status check_chained_off(const dr_tuning* tu) {
-    if (tu && (tu->flags & DR_TUNE_CHAINED))
-        return fail(DR_ERR_UNSUPPORTED, "the chained single pass (DR_TUNE_CHAINED) is switched off in this build");
+// Without a tuning, a sum of the identity view over one range (CONCAT) of
+// more than 2^22 binary32 / int32 elements runs the chained single pass:
+// the input is read from HBM once instead of twice (2^28 binary32 elements
+// in 16 segments: 500-508 us against 527-540 for the two passes; 2^30
+// int32 -> int64 2.96 ms against 3.14, -> int32 2.08 against 2.26), and its
+// carries, like the two passes', are sums in a fixed order. `tmp` holds
+// the tuning it stands for.
+static const dr_tuning* default_scan_tuning(const dr_table* t, int in_dt, int out_dt, int op, bool c64,
+                                            const dr_tuning* tu, dr_tuning& tmp) {
+    if (tu || !t || t->mode != DR_MODE_CONCAT || op != DR_OP_IDENTITY ||
+        t->total_length <= ((int64_t)1 << 22) || !find_scan_chain(in_dt, out_dt, op, c64, 16))
+        return tu;
+    tmp = dr_tuning{0, 16, DR_TUNE_CHAINED, 0};
+    return &tmp;
+}
+
+// The chained single pass (DR_TUNE_CHAINED), on request: sums of the
+// identity view of one range (CONCAT) at 16 items per thread, for the
+// dtypes find_scan_chain names. `fn` is its kernel when requested (and
+// nullptr otherwise).
+static dr_status chained_kernel(const dr_tuning* tu, const dr_table* t, int in_dt, int out_dt, int op,
+                                bool c64, bool sum, LaunchFn& fn) {
+    fn = nullptr;
+    if (!tu || !(tu->flags & DR_TUNE_CHAINED)) return DR_OK;
+    if (!sum) return fail(DR_ERR_UNSUPPORTED, "the chained single pass (DR_TUNE_CHAINED) runs sums only");
+    if (t && t->mode != DR_MODE_CONCAT)
+        return fail(DR_ERR_UNSUPPORTED, "the chained single pass (DR_TUNE_CHAINED) scans one range (CONCAT); "
+                                        "batches of ranges run the look-back or the two-pass form");
+    fn = find_scan_chain(in_dt, out_dt, op, c64, tu->items_per_thread ? tu->items_per_thread : 16);
+    if (!fn)
+        return fail(DR_ERR_UNSUPPORTED, "the chained single pass is built for sums of the identity view "
+                                        "(binary32, int32 -> int64 / int32) at 16 items per thread");
     return DR_OK;
 }
 
@@ -561,7 +592,11 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
         return fail(DR_ERR_INVALID_ARG, "unknown scan flags 0x%x", flags);
     if ((flags & DR_SCAN_CARRY_F32) && in != DR_F32 && in != DR_BF16)
         return fail(DR_ERR_INVALID_ARG, "DR_SCAN_CARRY_F32 applies to binary32/bfloat16 inputs only");
-    s = check_chained_off(tuning);
+    dr_tuning chained_dflt;
+    tuning = default_scan_tuning(table, in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, tuning,
+                                 chained_dflt);
+    LaunchFn chain = nullptr;
+    s = chained_kernel(tuning, table, in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, true, chain);
     if (s) return s;
     Prepared p;
     int items;
@@ -575,11 +610,13 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
                 ws_on ? wsu : scan_tuning(table, in, out_dtype, view->op, tuning, dflt), ws, ws_bytes, true,
                 view->op == DR_OP_IDENTITY, p, items);
     if (s) return s;
-    LaunchFn fn = scan_kernel(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items, p.block, tuning);
+    LaunchFn fn = chain ? chain
+                        : scan_kernel(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items, p.block, tuning);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
     p.a.alpha = view->alpha;
     p.a.flags = flags;
-    if (ws_on) p.a.flags |= kFlagSpecialized;
+    if (chain) p.a.flags |= kFlagChained;
+    else if (ws_on) p.a.flags |= kFlagSpecialized;
     else p.a.flags |= sum_scan_form(table, in, tuning);
     return launch(fn, p, stream, "inclusive_scan launch");
 }
@@ -646,7 +683,12 @@ dr_status dr_scan(const dr_table* table, const dr_view* view, int32_t out_dtype,
     }
     if (mm && tuning && (tuning->flags & (DR_TUNE_SPECIALIZED | DR_TUNE_CHAINED)))
         return fail(DR_ERR_UNSUPPORTED, "max / min scans run in the reduce-then-scan form only");
-    s = check_chained_off(tuning);
+    dr_tuning chained_dflt;
+    if (!mm)
+        tuning = default_scan_tuning(table, in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, tuning,
+                                     chained_dflt);
+    LaunchFn chain = nullptr;
+    s = chained_kernel(tuning, table, in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, !mm, chain);
     if (s) return s;
     Prepared p;
     int items;
@@ -662,12 +704,15 @@ dr_status dr_scan(const dr_table* table, const dr_view* view, int32_t out_dtype,
                 mm ? tuning : ws_on ? wsu : scan_tuning(table, in, out_dtype, view->op, tuning, dflt), ws, ws_bytes,
                 true, view->op == DR_OP_IDENTITY, p, items);
     if (s) return s;
-    LaunchFn fn = mm ? find_scan_minmax(in, out_dtype)
-                     : scan_kernel(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items, p.block, tuning);
+    LaunchFn fn = mm    ? find_scan_minmax(in, out_dtype)
+                  : chain ? chain
+                          : scan_kernel(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items, p.block,
+                                        tuning);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
     p.a.alpha = view->alpha;
     p.a.flags = flags;
-    if (ws_on) p.a.flags |= kFlagSpecialized;
+    if (chain) p.a.flags |= kFlagChained;
+    else if (ws_on) p.a.flags |= kFlagSpecialized;
     else if (!mm) p.a.flags |= sum_scan_form(table, in, tuning);
     if (combine == DR_COMBINE_MIN) p.a.flags |= kFlagMin;
     if (init) {
@@ -696,8 +741,9 @@ dr_status dr_scan_reduce(const dr_table* table, const dr_view* scan_view, const 
     if (!init) return fail(DR_ERR_INVALID_ARG, "init is NULL");
     if (!result && !(table && table->mode == DR_MODE_BATCH && table->n_segments == 0))
         return fail(DR_ERR_INVALID_ARG, "result is NULL");
-    s = check_chained_off(tuning);
-    if (s) return s;
+    if (tuning && (tuning->flags & DR_TUNE_CHAINED))
+        return fail(DR_ERR_UNSUPPORTED, "the chained single pass (DR_TUNE_CHAINED) is not built for the fused "
+                                        "scan + reduce");
     Prepared p;
     int items;
     dr_tuning wst;

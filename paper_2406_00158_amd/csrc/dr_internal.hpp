@@ -128,6 +128,9 @@ LaunchFn find_scan_reduce(int in_dt, int reduce_op, int acc, int items);
 // threads, or 4 / 8 items per thread): binary32 sums with binary64 carries,
 // plain (fused = false) or fused with the compensated dot.
 LaunchFn find_scan_wide(int in_dt, int out_dt, int op, bool carry64, bool fused, int acc, int items, int block);
+// The chained single pass (k_scan_chain.hip): sums of the identity view of
+// one range (CONCAT), binary32 and int32 -> int64 / int32, 16 items.
+LaunchFn find_scan_chain(int in_dt, int out_dt, int op, bool carry64, int items);
 LaunchFn find_broadcast_mul(int in_dt, int op, int items);
 LaunchFn find_black_scholes(int items);
 hipError_t launch_plan(const LaunchArgs& a, hipStream_t stream);     // prefix + tile -> segment map

@@ -754,337 +754,6 @@ hipError_t launch_scan_ws(const LaunchArgs& a, hipStream_t stream) {
     return hipLaunchCooperativeKernel(fn, dim3((uint32_t)resident), dim3(kWsThreads), args, 0, stream);
 }
 
-// ---------------------------------------------------------------------------
-// Chained single pass (switched off: not instantiated, never selected)
-// ---------------------------------------------------------------------------
-//
-// A GPU run of this form faulted (int32 -> int64 with 64 items per thread,
-// one tile per chunk, reverse, 2^25 elements, 16 segments), and the same
-// instance gave wrong carries at 2^30 forward; the cause has not been found
-// by reading the code, so the host never selects the form. The design, kept
-// here for the record:
-//
-// A grid of a few workgroups per CU takes chunks of P consecutive tiles (in
-// processing order) from a counter, one at a time, and runs every chunk in
-// two phases, one chunk apart:
-//   phase A  reads the chunk with plain loads (its lines stay in the L2 of
-//            the workgroup's XCD), forms every tile's total exactly as phase
-//            B will (and, fused, the tiles' reduce partials and their
-//            combine), and publishes the chunk's (has-head, total) pair; the
-//            last chunk of a superblock of kChainSB chunks to arrive folds
-//            the superblock's pairs with a fixed tree and publishes the
-//            running carry at the superblock's end, E(sb) = E(sb-1) (+)
-//            that fold;
-//   phase B  runs after the workgroup's next chunk has been through phase A:
-//            the chunk's carry is E(sb-1) (+) the fixed-tree fold of the
-//            pairs of the chunks before it in its superblock; the chunk is
-//            read again (from L2), each tile scanned in registers, its carry
-//            added, and written once.
-// HBM sees each input byte read once and each output byte written once.
-// Every carry is a fold in a fixed shape, so results repeat exactly and do
-// not depend on the grid. A workgroup waits only for chunks claimed before
-// its own, whose workgroups are running and publish their pairs before they
-// wait for anything, so every wait ends without co-residency; every wait is
-// also bounded (fault bit 2). (h, v) (+) (h2, v2) = (h | h2, h2 ? v2 : v + v2)
-// is the segmented sum: a head starts a BATCH range (the carry restarts).
-
-constexpr int kChainWaves = kBlock / 64;
-
-template <class C>
-struct SegPair {
-    C v;
-    int h;
-};
-
-template <class C>
-__device__ __forceinline__ SegPair<C> seg_op(SegPair<C> a, SegPair<C> b) {
-    return SegPair<C>{b.h ? b.v : a.v + b.v, a.h | b.h};
-}
-
-// Read a published (head, total) pair; false while it is not current.
-template <class C>
-__device__ __forceinline__ bool ws_read(const uint64_t* tw, uint32_t tag, SegPair<C>& p) {
-    const uint64_t q0 = atomic_ld(tw + kAggWord), q1 = atomic_ld(tw + kAggWord + 1);
-    const uint32_t t0 = (uint32_t)(q0 >> 32), t1 = (uint32_t)(q1 >> 32);
-    if (t0 != tag || (t1 != tag && t1 != (tag ^ kHeadBit))) return false;
-    p.v = from_bits<C>((uint64_t)(uint32_t)q0 | ((uint64_t)(uint32_t)q1 << 32));
-    p.h = t1 != tag;
-    return true;
-}
-
-// Fold of the published pairs of chunks [j0, lim) (lim - j0 <= kChainSB)
-// with a fixed tree: chunk j0 + i in thread i, a segmented DPP scan over
-// each wave, the waves in order. Every thread waits until the pairs it
-// holds are published (bounded; a timeout flags the fault and counts the
-// missing pairs as identities). Result valid in every thread.
-template <class C>
-__device__ __forceinline__ SegPair<C> chain_fold(const LaunchArgs& a, uint32_t tag, const uint64_t* tws, int64_t TW,
-                                                 int64_t j0, int64_t lim, SegPair<C>* s_w) {
-    const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
-    SegPair<C> mine{(C)0, 0};
-    const int64_t j = j0 + tid;
-    const bool need = tid < kChainSB && j < lim;
-    bool got = !need;
-    if (need) got = ws_read<C>(tws + j * TW, tag, mine);
-    if (!__syncthreads_and(got ? 1 : 0)) {
-        Deadline dl(a.spin_ticks);
-        while (true) {
-            if (!got) got = ws_read<C>(tws + j * TW, tag, mine);
-            if (__syncthreads_and(got ? 1 : 0)) break;
-            if (__syncthreads_or(tid == 0 && dl.passed())) {
-                if (tid == 0) flag_error(a, DR_DEVFLAG_TIMEOUT);
-                if (!got) mine = SegPair<C>{(C)0, 0};
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    // segmented inclusive scan over the wave (lanes without a source get the
-    // identity (0, 0)), lane 63 then holds the wave's fold
-    C sv = mine.v;
-    int sh = mine.h;
-    auto step = [&](C pv, int ph) {
-        if (!sh) sv = pv + sv;
-        sh = sh | ph;
-    };
-    step(dpp_move<DPP_ROW_SHR1, 0xf>(sv), dpp_move<DPP_ROW_SHR1, 0xf>(sh));
-    step(dpp_move<DPP_ROW_SHR2, 0xf>(sv), dpp_move<DPP_ROW_SHR2, 0xf>(sh));
-    step(dpp_move<DPP_ROW_SHR4, 0xf>(sv), dpp_move<DPP_ROW_SHR4, 0xf>(sh));
-    step(dpp_move<DPP_ROW_SHR8, 0xf>(sv), dpp_move<DPP_ROW_SHR8, 0xf>(sh));
-    step(dpp_move<DPP_ROW_BCAST15, 0xa>(sv), dpp_move<DPP_ROW_BCAST15, 0xa>(sh));
-    step(dpp_move<DPP_ROW_BCAST31, 0xc>(sv), dpp_move<DPP_ROW_BCAST31, 0xc>(sh));
-    if (l == 63) s_w[w] = SegPair<C>{sv, sh};
-    __syncthreads();
-    SegPair<C> f = s_w[0];
-    for (int i = 1; i < kChainWaves; ++i) f = seg_op(f, s_w[i]);
-    __syncthreads();   // s_w is rewritten by the next fold
-    return f;
-}
-
-// The running carry at the end of superblock sb (thread 0; bounded wait).
-template <class C>
-__device__ __forceinline__ C chain_end(const LaunchArgs& a, uint32_t tag, const uint64_t* ew, int64_t sb) {
-    uint64_t bits = 0;
-    if (!tagged_load(ew + 2 * sb, tag, bits)) {
-        Deadline dl(a.spin_ticks);
-        while (!tagged_load(ew + 2 * sb, tag, bits)) {
-            if (dl.passed()) {
-                flag_error(a, DR_DEVFLAG_TIMEOUT);
-                return (C)0;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    return from_bits<C>(bits);
-}
-
-template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV, int P>
-__global__ __launch_bounds__(kBlock) void k_scan_chain(LaunchArgs a) {
-    // int32 -> int64: 8-byte input vectors, as in the apply pass of the
-    // two-pass form (each lane's outputs are one dense 16-byte store)
-    constexpr int V = (IDT == DR_I32 && ODT == DR_I64) ? 2 : vwidth<IDT>();
-    constexpr int SLOTS = ITEMS / V;
-    constexpr int WAVES = kChainWaves;
-    constexpr bool ZIP = zip_view<IDT, OP, false, 0>();          // the scanned view reads in[1]
-    constexpr bool ZIPA = zip_view<IDT, OP, FUSED, ROP>();       // phase A reads in[1]
-    using L = local_t<IDT>;
-    using C = carry_t<IDT, C64>;
-    __shared__ L s_wtot[WAVES];
-    __shared__ float s_rs[WAVES], s_rc[WAVES];
-    __shared__ double s_rd[WAVES];
-    __shared__ C s_tot[2][P];
-    __shared__ int s_head[2][P], s_ok[2][P];
-    __shared__ SegPair<C> s_fold[WAVES];
-    __shared__ int s_claim, s_last;
-    __shared__ C s_carry;
-
-    const uint32_t tag = begin_launch(a.ws);
-    TileMap tm;
-    tm.init(a);
-    if (!tm.ok) return;
-    const int64_t T = tm.total_tiles;
-    if (T == 0) {
-        if (FUSED && blockIdx.x == 0 && threadIdx.x == 0) {   // no tiles at all
-            if (a.mode == DR_MODE_BATCH) write_all_init<double>(a);
-            else write_result<double>(a, 0, 0.0);
-        }
-        return;
-    }
-    const int64_t NC = (T + P - 1) / P;
-    const int64_t TW = a.lay.tile_words;
-    uint64_t* tws = (uint64_t*)(a.ws + a.lay.off_tile);
-    uint32_t* pc = (uint32_t*)(a.ws + a.lay.off_pipe);
-    uint64_t* ew = (uint64_t*)(a.ws + a.lay.off_pipe_e);
-    const int w = threadIdx.x >> 6, l = lane_id();
-    const L alpha = (L)a.alpha;
-    auto phys = [&](int64_t r) { return REV ? T - 1 - r : r; };
-
-    auto claim = [&]() -> int64_t {
-        if (threadIdx.x == 0) s_claim = (int)atomic_add32(pc, 1u);
-        __syncthreads();
-        const int64_t c = s_claim;
-        __syncthreads();
-        return c;
-    };
-
-    // phase A of chunk c into buffer b
-    auto phase_a = [&](int64_t c, int b) {
-        const int64_t r0 = c * P;
-        const int np = (int)(T - r0 < P ? T - r0 : P);
-        vec<IDT, V> xa[SLOTS], ya[SLOTS], xb[SLOTS], yb[SLOTS];
-        SegInfo sa, sb_;
-        bool oka = false, okb = false;
-        auto issue = [&](int p, SegInfo& si, vec<IDT, V> (&x)[SLOTS], vec<IDT, V> (&y)[SLOTS]) -> bool {
-            const int64_t t = phys(r0 + p);
-            if (!tm.find(a, t, si)) return false;
-            const int64_t u0 = (t - si.first) * a.tile;
-            load_slots<IDT, SLOTS, V, false>(x, si.in0, si, u0, w, l, REV);
-            if constexpr (ZIPA) load_slots<IDT, SLOTS, V, false>(y, si.in1, si, u0, w, l, REV);
-            return true;
-        };
-        auto consume = [&](int p, bool ok, const SegInfo& si, const vec<IDT, V> (&x)[SLOTS],
-                           const vec<IDT, V> (&y)[SLOTS]) {
-            const int64_t r = r0 + p, t = phys(r);
-            float fws = 0.0f, fwc = 0.0f;
-            double fwd = 0.0;
-            if (ok) {
-                L v[SLOTS][V];
-                L base[SLOTS];
-                const int64_t u0 = (t - si.first) * a.tile;
-                const L wt = tile_values<IDT, OP, ZIP, SLOTS, REV, kCmbSum, V>(x, y, alpha, v, base, false, si, u0,
-                                                                           tile_full<V, SLOTS>(si, u0));
-                if constexpr (FUSED) fused_wave<IDT, ROP, RACC, SLOTS>(x, y, fws, fwc, fwd);
-                if (l == 0) {
-                    s_wtot[w] = wt;
-                    if constexpr (FUSED) {
-                        s_rs[w] = fws;
-                        s_rc[w] = fwc;
-                        s_rd[w] = fwd;
-                    }
-                }
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                L tl = (L)0;
-                if (ok)
-                    for (int i = 0; i < WAVES; ++i) tl += s_wtot[i];
-                s_tot[b][p] = ok ? (C)tl : (C)0;
-                s_head[b][p] = (!ok || r == stop_of<REV>(a, si, T)) ? 1 : 0;
-                s_ok[b][p] = ok ? 1 : 0;
-            }
-            if constexpr (FUSED) {
-                if (ok && threadIdx.x < 64) {   // wave 0 publishes the tile's partial and combines
-                    double part = 0.0;
-                    if (l == 0) part = fused_block<IDT, RACC, WAVES>(s_rs, s_rc, s_rd);
-                    if (a.mode == DR_MODE_BATCH) combine_tile_batch<double>(a, tag, t, si, part);
-                    else combine_member<double>(a, tag, 0, 0, t, T, 0, part);
-                }
-            }
-            __syncthreads();   // s_wtot and the fused partials are rewritten by the next tile
-        };
-        oka = issue(0, sa, xa, ya);
-        for (int p = 0; p < np; p += 2) {
-            if (p + 1 < np) okb = issue(p + 1, sb_, xb, yb);
-            consume(p, oka, sa, xa, ya);
-            if (p + 1 >= np) break;
-            if (p + 2 < np) oka = issue(p + 2, sa, xa, ya);
-            consume(p + 1, okb, sb_, xb, yb);
-        }
-        // publish the chunk's pair; the superblock's last arrival publishes E(sb)
-        const int64_t sbk = c / kChainSB, c0 = sbk * kChainSB;
-        const int64_t nsb = NC - c0 < kChainSB ? NC - c0 : kChainSB;
-        if (threadIdx.x == 0) {
-            SegPair<C> f{s_tot[b][0], s_head[b][0]};
-            for (int p = 1; p < np; ++p) f = seg_op(f, SegPair<C>{s_tot[b][p], s_head[b][p]});
-            ws_publish<C>(tws + c * TW, tag, f.h != 0, f.v);
-            s_last = atomic_add32(pc + 1 + sbk, 1u) == (uint32_t)(nsb - 1);
-        }
-        __syncthreads();
-        if (!s_last) return;
-        const SegPair<C> tot = chain_fold<C>(a, tag, tws, TW, c0, c0 + nsb, s_fold);
-        if (threadIdx.x == 0) {
-            const C prev = sbk > 0 ? chain_end<C>(a, tag, ew, sbk - 1) : (C)0;
-            tagged_store(ew + 2 * sbk, tag, to_bits(tot.h ? tot.v : prev + tot.v));
-        }
-    };
-
-    // phase B of chunk c from buffer b
-    auto phase_b = [&](int64_t c, int b) {
-        const int64_t sbk = c / kChainSB, c0 = sbk * kChainSB;
-        const SegPair<C> pre = chain_fold<C>(a, tag, tws, TW, c0, c, s_fold);
-        if (threadIdx.x == 0) {
-            const C prev = sbk > 0 ? chain_end<C>(a, tag, ew, sbk - 1) : (C)0;
-            s_carry = pre.h ? pre.v : prev + pre.v;
-        }
-        __syncthreads();
-        C run = s_carry;
-        const int64_t r0 = c * P;
-        const int np = (int)(T - r0 < P ? T - r0 : P);
-        for (int p = 0; p < np; ++p) {
-            if (s_head[b][p]) run = (C)0;
-            const C excl = run;
-            run = run + s_tot[b][p];
-            if (!s_ok[b][p]) continue;   // malformed row (flagged)
-            const int64_t t = phys(r0 + p);
-            SegInfo si;
-            if (!tm.find(a, t, si)) continue;
-            const int64_t u0 = (t - si.first) * a.tile;
-            const bool full = tile_full<V, SLOTS>(si, u0);
-            vec<IDT, V> x[SLOTS], y[SLOTS];
-            load_pair<ZIP, IDT, SLOTS, V>(x, y, si, u0, w, l, REV);
-            L v[SLOTS][V];
-            L base[SLOTS];
-            const L wt = tile_values<IDT, OP, ZIP, SLOTS, REV, kCmbSum, V>(x, y, alpha, v, base, false, si, u0, full);
-            if (l == 0) s_wtot[w] = wt;
-            __syncthreads();
-            L woff = (L)0;
-            for (int i = 0; i < w; ++i) woff += s_wtot[i];
-            const C eo = (a.flags & kFlagHasInit) ? init_carry<C, IDT>(a) + excl : excl;
-            tile_write<IDT, ODT, C64, SLOTS, REV, kCmbSum, V>(v, base, eo, woff, si, u0, w, l, full,
-                                                           (a.flags & DR_SCAN_EXCLUSIVE) != 0);
-            __syncthreads();   // s_wtot is rewritten by the next tile
-        }
-    };
-
-    int64_t cur = claim();
-    int buf = 0;
-    if (cur < NC) phase_a(cur, buf);
-    while (cur < NC) {
-        const int64_t nxt = claim();
-        if (nxt < NC) phase_a(nxt, buf ^ 1);
-        phase_b(cur, buf);
-        cur = nxt;
-        buf ^= 1;
-    }
-}
-
-// Tiles per chunk of the chained pass: chunks of about 64 KiB of the
-// scanned input (measured best at 2^28 binary32: 4 tiles of 16 KiB).
-template <int IDT, int ITEMS>
-constexpr int chain_tiles() {
-    constexpr int bytes = kBlock * ITEMS * esize<IDT>();
-    return bytes >= 65536 ? 1 : 65536 / bytes;
-}
-
-template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV>
-hipError_t launch_scan_chain(const LaunchArgs& a, hipStream_t stream) {
-    constexpr int P = chain_tiles<IDT, ITEMS>();
-    // two workgroups per CU: more leave too many chunks between a chunk's two
-    // reads for the L2 to keep it
-    static const int grid = [] {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-            cus = 1;
-        return 2 * cus;
-    }();
-    const int64_t chunks = (a.tmax + P - 1) / P;
-    const int64_t g = chunks < grid ? (chunks < 1 ? 1 : chunks) : grid;
-    hipLaunchKernelGGL((k_scan_chain<IDT, ODT, OP, C64, FUSED, ROP, RACC, ITEMS, REV, P>), dim3((uint32_t)g),
-                       dim3(kBlock), 0, stream, a);
-    return hipGetLastError();
-}
-
 template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int ITEMS, bool REV, int CMB>
 hipError_t launch_scan_dir(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
     if constexpr (CMB == kCmbSum) {
@@ -1115,16 +784,12 @@ template <int IDT, int ODT, int OP, bool C64, bool FUSED, int ROP, int RACC, int
 hipError_t launch_scan(const LaunchArgs& a, int64_t grid, hipStream_t stream) {
     constexpr bool WS = CMB == kCmbSum && ws_form<IDT, ODT, OP, FUSED, ITEMS>();
     const bool ws = WS && (a.flags & kFlagSpecialized) != 0;
-    const bool chain = CMB == kCmbSum && (a.flags & kFlagChained) != 0;
     // the prologue (epoch tag, zeroed counters) serves the single-pass forms
     // and the fused reduction's combine
-    if (FUSED || ws || chain || (CMB == kCmbSum && (a.flags & kFlagTilePerBlock))) {
+    if (FUSED || ws || (CMB == kCmbSum && (a.flags & kFlagTilePerBlock))) {
         hipError_t e = launch_prologue(a, stream);
         if (e != hipSuccess) return e;
     }
-    // the chained single pass (k_scan_chain) is switched off: the host never
-    // sets kFlagChained (dr_api.cpp, check_chained_off), and it is not built
-    if (chain) return hipErrorNotSupported;
     if constexpr (WS) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (ws && hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {

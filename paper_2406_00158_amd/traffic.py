@@ -27,7 +27,8 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["dr_device.hpp", "dr_internal.hpp", "dr_combine.hpp", "k_scan_core.hpp", "k_elementwise.hip",
-                  "k_reduce.hip", "k_scan.hip", "k_scan_wide.hip", "k_plan.hip", "dr_api.cpp", "dr_static.hip"]
+                  "k_reduce.hip", "k_scan.hip", "k_scan_wide.hip", "k_scan_chain.hip", "k_plan.hip", "dr_api.cpp",
+                  "dr_static.hip"]
 COPY_ELEMS = 1 << 28
 
 

@@ -30,14 +30,30 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(B.EXPORTS)
 
 
-def test_chained_scan_form_is_switched_off():
-    t, keep = _host_table([((A,), (O,), 10)], 10)
+def test_chained_scan_form_scope():
+    """The chained single pass scans one range (CONCAT) of binary32 or int32
+    sums at 16 items per thread; anything else is refused on the host."""
+    L = B.lib()
     v = B.make_view("identity", B.DR_F32)
     tu = B.make_tuning(16, B.DR_TUNE_CHAINED)
-    L = B.lib()
-    assert L.dr_inclusive_scan(ctypes.byref(t), ctypes.byref(v), B.DR_F32, 0, 0x40000000, 1 << 30,
+    sup = lambda algo, view, odt, t: L.dr_tuning_supported(algo, ctypes.byref(view), odt, ctypes.byref(t))
+    assert sup(B.DR_ALGO_SCAN, v, B.DR_F32, tu) == 1
+    assert sup(B.DR_ALGO_SCAN, B.make_view("identity", B.DR_I32), B.DR_I64, tu) == 1
+    assert sup(B.DR_ALGO_SCAN, B.make_view("identity", B.DR_I32), B.DR_I32, tu) == 1
+    assert sup(B.DR_ALGO_SCAN, B.make_view("identity", B.DR_F64), B.DR_F64, tu) == 0
+    assert sup(B.DR_ALGO_SCAN, B.make_view("square", B.DR_F32), B.DR_F32, tu) == 0
+    assert sup(B.DR_ALGO_SCAN, v, B.DR_F32, B.make_tuning(32, B.DR_TUNE_CHAINED)) == 0
+    assert sup(B.DR_ALGO_SCAN_REDUCE, v, B.DR_F32, tu) == 0
+    tb, keep_b = _host_table([((A,), (O,), 10)], 10)
+    tb.mode = B.DR_MODE_BATCH
+    assert L.dr_inclusive_scan(ctypes.byref(tb), ctypes.byref(v), B.DR_F32, 0, 0x40000000, 1 << 30,
                                ctypes.byref(tu), None) == B.DR_ERR_UNSUPPORTED
-    assert b"switched off" in L.dr_last_error()
+    assert b"CONCAT" in L.dr_last_error()
+    init = ctypes.c_double(0.0)
+    assert L.dr_scan(ctypes.byref(tb), ctypes.byref(v), B.DR_F32, B.DR_COMBINE_MAX, 0, ctypes.byref(init),
+                     0x40000000, 1 << 30, ctypes.byref(tu), None) == B.DR_ERR_UNSUPPORTED
+    del keep_b
+    t, keep = _host_table([((A,), (O,), 10)], 10)
     tu2 = B.make_tuning(16, B.DR_TUNE_TILE_PER_BLOCK | B.DR_TUNE_TWO_PASS)
     assert L.dr_inclusive_scan(ctypes.byref(t), ctypes.byref(v), B.DR_F32, 0, 0x40000000, 1 << 30,
                                ctypes.byref(tu2), None) == B.DR_ERR_INVALID_ARG   # one form flag at most

@@ -93,14 +93,16 @@ def test_triad_and_dot_2_28():
     assert rel <= REL_COMPENSATED
 
 
+@pytest.mark.parametrize("form", ["default", "chained"])
 @pytest.mark.parametrize("out_dt", [B.DR_I64, B.DR_I32])
-def test_int_scan_2_30(out_dt):
+def test_int_scan_2_30(out_dt, form):
     t = _workload("scan_int")
     L = t["lengths"]
-    announce("int scan 2^30", out_dt)
+    announce("int scan 2^30", out_dt, form)
     k = _to_dev(t["k"])
     out = torch.empty(k.numel(), dtype=B.TORCH_DTYPE[out_dt], device=dev())
-    B.dr_inclusive_scan(B.segments([_pieces(k, L)], [_pieces(out, L)]), B.make_view("identity", B.DR_I32), out_dt)
+    B.dr_inclusive_scan(B.segments([_pieces(k, L)], [_pieces(out, L)]), B.make_view("identity", B.DR_I32), out_dt,
+                        tuning=B.make_tuning(16, B.DR_TUNE_CHAINED) if form == "chained" else None)
     del k
     got = dev_to_np(out)
     del out
@@ -109,7 +111,7 @@ def test_int_scan_2_30(out_dt):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("form", ["default", "two_pass", "specialized"])
+@pytest.mark.parametrize("form", ["default", "two_pass", "chained", "specialized"])
 def test_fp32_scan_2_28_f64_carry(form):
     t = _workload("scan_fp")
     L = t["lengths"]
@@ -117,6 +119,7 @@ def test_fp32_scan_2_28_f64_carry(form):
     x = _to_dev(t["x"])
     out = torch.empty_like(x)
     tuning = {"default": None, "two_pass": B.make_tuning(None, B.DR_TUNE_TWO_PASS),
+              "chained": B.make_tuning(16, B.DR_TUNE_CHAINED),
               "specialized": B.make_tuning(B.WS_ITEMS[B.DR_F32], B.DR_TUNE_SPECIALIZED)}[form]
     B.dr_inclusive_scan(B.segments([_pieces(x, L)], [_pieces(out, L)]), B.make_view("identity", B.DR_F32),
                         B.DR_F32, tuning=tuning)

@@ -54,9 +54,7 @@ def _init(in_dt, which):
 @pytest.mark.parametrize("in_dt,out_dt", SCAN_PAIRS)
 @pytest.mark.parametrize("mode", ["concat", "batch"])
 @pytest.mark.parametrize("reverse", [False, True])
-@pytest.mark.parametrize("form", ["two_pass", pytest.param("chained", marks=pytest.mark.skip(
-    reason="the chained single pass is switched off: a GPU run of it faulted and the cause is not found")),
-    "look_back", "specialized"])
+@pytest.mark.parametrize("form", ["two_pass", "chained", "look_back", "specialized"])
 def test_sum_scan_exclusive_with_init(seg_name, lengths, in_dt, out_dt, mode, reverse, form):
     if form == "specialized" and out_dt == B.DR_I64:
         pytest.skip("int32 -> int64 scans keep the two passes")
@@ -70,7 +68,13 @@ def test_sum_scan_exclusive_with_init(seg_name, lengths, in_dt, out_dt, mode, re
     tu = B.make_tuning(items, {"two_pass": B.DR_TUNE_TWO_PASS, "chained": B.DR_TUNE_CHAINED,
                                "look_back": B.DR_TUNE_TILE_PER_BLOCK, "specialized": B.DR_TUNE_SPECIALIZED}[form])
     flags = B.DR_SCAN_EXCLUSIVE | (B.DR_SCAN_REVERSE if reverse else 0)
-    B.dr_scan(tab, B.make_view("identity", in_dt), out_dt, B.DR_COMBINE_SUM, flags, init, tuning=tu)
+    call = lambda: B.dr_scan(tab, B.make_view("identity", in_dt), out_dt, B.DR_COMBINE_SUM, flags, init, tuning=tu)
+    if form == "chained" and (mode == "batch" or in_dt not in (B.DR_F32, B.DR_I32)):
+        with pytest.raises(B.DrError) as e:   # built for one range of binary32 / int32
+            call()
+        assert e.value.status == B.DR_ERR_UNSUPPORTED
+        return
+    call()
     omode = O.BATCH if mode == "batch" else O.CONCAT
     got = gather(outs)
     if in_dt == B.DR_I32:

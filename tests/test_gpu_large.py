@@ -1,7 +1,8 @@
-"""Scan parity at 2^25 + a ragged tail, in the default form and with the
+"""Scan parity at 2^25 + a ragged tail, in the default form, with the
 reduce-then-scan form named explicitly (its first pass gives every
-workgroup a chunk of several tiles, with segment heads inside chunks), as at
-the benchmark's sizes. Reverse scans (the scan adjoint), exclusive sums with an initial
+workgroup a chunk of several tiles, with segment heads inside chunks) and
+with the chained single pass (one range only), as at the benchmark's
+sizes. Reverse scans (the scan adjoint), exclusive sums with an initial
 value and max / min scans, over one distributed range (CONCAT, 16 Dirichlet
 segments) and over 300 ragged independent ranges (BATCH, a planned table),
 against the oracle: integers and max / min exactly, binary32 sums within
@@ -45,10 +46,13 @@ def _pieces(t, lengths):
     return out
 
 
-FORMS = {"default": None, "two_pass": B.make_tuning(None, B.DR_TUNE_TWO_PASS)}
+FORMS = {"default": None, "two_pass": B.make_tuning(None, B.DR_TUNE_TWO_PASS),
+         "chained": B.make_tuning(16, B.DR_TUNE_CHAINED)}
 
 
 def _run(in_dt, out_dt, mode, combine, flags, init, form="default"):
+    if form == "chained" and mode == "batch":
+        pytest.skip("the chained single pass scans one range (CONCAT); batches are refused on the host")
     lengths = _lengths(mode)
     x = _data(in_dt)
     xd = torch.from_numpy(x).to(dev())

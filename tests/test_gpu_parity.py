@@ -187,12 +187,19 @@ SCAN_CASES = [(B.DR_I32, B.DR_I64), (B.DR_I32, B.DR_I32), (B.DR_F32, B.DR_F32), 
 
 # the library's default (no tuning: the two passes, or for small int32 scans
 # the look-back), and each form requested explicitly: the reduce-then-scan
-# passes, the chained single pass (switched off: its cases are skipped), the
+# passes, the chained single pass (one range, sums of binary32 / int32), the
 # look-back (one workgroup per tile in block-index order) and the specialised
 # waves
-CHAINED_OFF = "the chained single pass is switched off: a GPU run of it faulted and the cause is not found"
-SCAN_FORMS = ["default", "two_pass", pytest.param("chained", marks=pytest.mark.skip(reason=CHAINED_OFF)),
-              "look_back", "specialized"]
+SCAN_FORMS = ["default", "two_pass", "chained", "look_back", "specialized"]
+CHAIN_BUILT = {(B.DR_F32, B.DR_F32), (B.DR_I32, B.DR_I64), (B.DR_I32, B.DR_I32)}
+
+
+def chained_refused(call):
+    """A chained-form call outside what the form is built for: refused on the
+    host (DR_ERR_UNSUPPORTED) before anything is enqueued."""
+    with pytest.raises(B.DrError) as e:
+        call()
+    assert e.value.status == B.DR_ERR_UNSUPPORTED
 FORM_FLAG = {"two_pass": B.DR_TUNE_TWO_PASS, "chained": B.DR_TUNE_CHAINED, "look_back": B.DR_TUNE_TILE_PER_BLOCK}
 
 
@@ -228,8 +235,12 @@ def test_inclusive_scan(seg_name, lengths, in_dt, out_dt, mode, reverse, form):
         x = x * 10_000_000                                  # the int32 output wraps
     outs = empty_like_segments(lengths, B.TORCH_DTYPE[out_dt], "separate")
     tab, _ = _table([x], lengths, layout, outs=[outs], mode=mode, offsets=(offs or [0])[:1])
-    B.dr_inclusive_scan(tab, B.make_view(op, in_dt), out_dt, B.DR_SCAN_REVERSE if reverse else 0,
-                        tuning=_scan_tuning(form, in_dt=in_dt))
+    call = lambda: B.dr_inclusive_scan(tab, B.make_view(op, in_dt), out_dt, B.DR_SCAN_REVERSE if reverse else 0,
+                                       tuning=_scan_tuning(form, in_dt=in_dt))
+    if form == "chained" and (mode == "batch" or (in_dt, out_dt) not in CHAIN_BUILT):
+        chained_refused(call)
+        return
+    call()
     got = gather(outs)
     omode = O.BATCH if mode == "batch" else O.CONCAT
     if in_dt == B.DR_I32:
@@ -322,9 +333,13 @@ def test_scan_reduce_fused(mode, reverse, form):
     tab, _ = _table([x, y], lengths, "carved", outs=[outs], mode=mode, offsets=[0, 0])
     nres = len(lengths) if mode == "batch" else 1
     res = torch.zeros(nres, dtype=torch.float64, device=dev())
-    B.dr_scan_reduce(tab, B.make_view("identity", B.DR_F32), B.make_view("mul", B.DR_F32),
-                     B.DR_ACC_COMPENSATED, 0.0, res, B.DR_SCAN_REVERSE if reverse else 0,
-                     tuning=_scan_tuning(form, fused=True))
+    call = lambda: B.dr_scan_reduce(tab, B.make_view("identity", B.DR_F32), B.make_view("mul", B.DR_F32),
+                                    B.DR_ACC_COMPENSATED, 0.0, res, B.DR_SCAN_REVERSE if reverse else 0,
+                                    tuning=_scan_tuning(form, fused=True))
+    if form == "chained":
+        chained_refused(call)   # not built for the fused scan + reduce
+        return
+    call()
     omode = O.BATCH if mode == "batch" else O.CONCAT
     ref, absp = O.scan(I.split(x, lengths), None, O.F32, O.IDENTITY, mode=omode, reverse=reverse, want_abs=True)
     ref, absp = np.concatenate(ref), np.concatenate(absp)
