@@ -5,8 +5,10 @@
 // The paper scans each segment locally, scans the segment totals, then adds
 // each segment's offset in a second read-write pass over the data (the
 // extra pass it blames for the scan's drop from one to two tiles, section
-// 5.1). Three forms are built here; every one writes each output once:
-//  - reduce-then-scan (the default): a read-only pass forms every tile's
+// 5.1). Three forms are built here, and the chained single pass for one
+// long range in k_scan_chain.hip; every one writes each output once:
+//  - reduce-then-scan (the default, except for the CONCAT sums past 2^22
+//    elements that take the chained pass): a read-only pass forms every tile's
 //    total, one small kernel scans the per-chunk totals, and the apply pass
 //    re-reads the input, scans each tile in registers and adds its carry
 //    (the input is read twice; carries are sums in a fixed order);

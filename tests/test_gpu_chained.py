@@ -128,3 +128,38 @@ def test_chained_is_the_default_for_one_long_range_and_runs_in_place():
     got = gather(segs)
     assert np.array_equal(got.view(np.uint32), asked.view(np.uint32))
     _check(B.DR_F32, B.DR_F32, L, x, got, False)
+
+
+def test_chained_under_graph_replay():
+    """The chained pass captured into a graph (its counters are zeroed by a
+    kernel, not a memset node): every replay, with eager work between them,
+    equals the eager call bit for bit."""
+    n = SIZES[0]
+    announce("chained graph replay", n)
+    L = _lengths(n, 21)
+    x = _data(B.DR_F32, n, 22)
+    segs, buf = carve(x, L, offset=1)
+    outs = empty_like_segments(L, torch.float32, "carved")
+    tab = B.segments([segs], [outs])
+    view = B.make_view("identity", B.DR_F32)
+    ws = B.Workspace(dev())
+    call = lambda: B.dr_inclusive_scan(tab, view, B.DR_F32, workspace=ws, host_check=False, tuning=CHAIN)
+    call()
+    torch.cuda.synchronize()
+    eager = gather(outs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        call()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    for k in range(3):
+        for o in outs:
+            o.fill_(float(k))                   # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(gather(outs).view(np.uint32), eager.view(np.uint32)), k
+    assert ws.device_status() == 0
