@@ -610,8 +610,8 @@ dr_status dr_inclusive_scan(const dr_table* table, const dr_view* view, int32_t 
                 ws_on ? wsu : scan_tuning(table, in, out_dtype, view->op, tuning, dflt), ws, ws_bytes, true,
                 view->op == DR_OP_IDENTITY, p, items);
     if (s) return s;
-    LaunchFn fn = chain ? chain
-                        : scan_kernel(in, out_dtype, view->op, (flags & DR_SCAN_CARRY_F32) == 0, items, p.block, tuning);
+    const bool c64 = (flags & DR_SCAN_CARRY_F32) == 0;
+    LaunchFn fn = chain ? chain : scan_kernel(in, out_dtype, view->op, c64, items, p.block, tuning);
     if (!fn) return fail(DR_ERR_UNSUPPORTED, "scan kernel not built for this combination");
     p.a.alpha = view->alpha;
     p.a.flags = flags;

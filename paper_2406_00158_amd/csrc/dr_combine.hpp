@@ -103,7 +103,8 @@ __device__ __forceinline__ void combine_member(const LaunchArgs& a, uint32_t tag
     }
     if (!readlane(last, 0)) return;
     P acc = id;
-    for (int64_t g = l; g < ngroups; g += 64) acc = cmb_op<CMB>(acc, wait_tagged<P>(a, gpart + (slot0 + g) * 2, tag), mn);
+    for (int64_t g = l; g < ngroups; g += 64)
+        acc = cmb_op<CMB>(acc, wait_tagged<P>(a, gpart + (slot0 + g) * 2, tag), mn);
     const P tot = wave_reduce_cmb<CMB>(acc, mn);
     if (l == 0) write_result<P, CMB>(a, unit, tot);
 }
