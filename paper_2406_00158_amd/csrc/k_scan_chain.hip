@@ -143,6 +143,38 @@ __device__ __forceinline__ bool chain_load_full(const LaunchArgs& a, const SegIn
     return true;
 }
 
+// Whether the P tiles of the chunk from processing index r0 all exist and
+// are full tiles of the segment `si` (which the caller found holds them).
+template <int V, int SLOTS, bool REV, int P>
+__device__ __forceinline__ bool chain_chunk_full(const LaunchArgs& a, const SegInfo& si, int64_t T, int64_t r0) {
+    if (r0 + P > T) return false;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int64_t t = REV ? T - 1 - (r0 + p) : r0 + p;
+        if (!tile_full<V, SLOTS>(si, (t - si.first) * a.tile)) return false;
+    }
+    return true;
+}
+
+// Phase B's re-read of one full tile (processing index r) of segment `si`:
+// unchecked non-temporal loads (the last use of the lines).
+template <int IDT, int V, int SLOTS, bool REV>
+__device__ __forceinline__ void chain_load_tile(const LaunchArgs& a, const SegInfo& si, int64_t T, int64_t r,
+                                                vec<IDT, V> (&x)[SLOTS], int w, int l) {
+    using R = typename vbits<V * esize<IDT>()>::T;
+    constexpr int64_t NV = (int64_t)kBlock * SLOTS;
+    const int64_t p0 = (int64_t)(w * SLOTS) * 64 + l;
+    const int64_t q0 = REV ? (NV - 1 - p0) : p0;
+    const int64_t step = REV ? -64 * (int64_t)sizeof(R) : 64 * (int64_t)sizeof(R);
+    const int64_t t = REV ? T - 1 - r : r;
+    const char* b = (const char*)si.in0 + ((t - si.first) * a.tile - si.shift + q0 * V) * esize<IDT>();
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const R wv = __builtin_nontemporal_load((const R*)(b + s * step));
+        __builtin_memcpy(&x[s], &wv, sizeof(R));
+    }
+}
+
 // A tile's total for the chunk totals (phase A): each thread sums each of
 // its vectors serially and the vector sums pairwise, then a DPP wave sum;
 // the caller adds the waves in order. A fixed order, so totals repeat
@@ -297,6 +329,35 @@ __global__ __launch_bounds__(kBlock) void k_scan_chain(LaunchArgs a) {
             const int64_t sbk = cur / kChainSB, c0 = sbk * kChainSB;
             SegInfo sc;
             const bool one = chain_segment(a, tm, T, r0b, P, REV, sc);   // uniform
+            if (one && chain_chunk_full<V, SLOTS, REV, P>(a, sc, T, r0b)) {
+                // the common case, pipelined: each tile's re-read is issued
+                // before the previous tile's stores (loads and stores share
+                // one in-order counter, so a load issued after a store would
+                // wait for the store), and the first one before the carry
+                // wait
+                X xb[2][SLOTS];
+                chain_load_tile<IDT, V, SLOTS, REV>(a, sc, T, r0b, xb[0], w, l);
+                C run = chain_sum<C>(a, tag, tws, TW, c0, cur, sbk > 0 ? ew + 2 * (sbk - 1) : nullptr, s_w);
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if (p + 1 < P) chain_load_tile<IDT, V, SLOTS, REV>(a, sc, T, r0b + p + 1, xb[(p + 1) & 1], w, l);
+                    const C excl = run;
+                    run = run + s_tot[buf][p];
+                    const int64_t t = REV ? T - 1 - (r0b + p) : r0b + p;
+                    const int64_t u0 = (t - sc.first) * a.tile;
+                    L v[SLOTS][V];
+                    L base[SLOTS];
+                    const L wt = tile_values<IDT, DR_OP_IDENTITY, false, SLOTS, REV, kCmbSum, V>(
+                        xb[p & 1], xb[p & 1], (L)0, v, base, false, sc, u0, true);
+                    if (l == 0) s_wt[w] = wt;
+                    __syncthreads();
+                    L woff = (L)0;
+                    for (int i = 0; i < w; ++i) woff += s_wt[i];
+                    tile_write<IDT, ODT, C64, SLOTS, REV, kCmbSum, V>(v, base, init + excl, woff, sc, u0, w, l, true,
+                                                                      exc);
+                    __syncthreads();   // s_wt is rewritten by the next tile
+                }
+            } else {
             C run = chain_sum<C>(a, tag, tws, TW, c0, cur, sbk > 0 ? ew + 2 * (sbk - 1) : nullptr, s_w);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
@@ -323,6 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_chain(LaunchArgs a) {
                 tile_write<IDT, ODT, C64, SLOTS, REV, kCmbSum, V>(v, base, init + excl, woff, si, u0, w, l, full,
                                                                   exc);
                 __syncthreads();   // s_wt is rewritten by the next tile
+            }
             }
         }
         if (nxt >= NC) break;
