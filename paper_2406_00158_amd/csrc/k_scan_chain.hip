@@ -202,11 +202,17 @@ __device__ __forceinline__ local_t<IDT> chain_tile_sum(const vec<IDT, V> (&x)[SL
 
 template <int IDT, int ODT, bool C64, bool REV>
 struct Chain {
+    // phase B: int32 -> int64 reads 8-byte vectors, so that each lane's
+    // outputs are one 16-byte store; phase A only sums, in any layout, so it
+    // always reads whole 16-byte vectors (the same lines)
     static constexpr int V = (IDT == DR_I32 && ODT == DR_I64) ? 2 : vwidth<IDT>();
     static constexpr int SLOTS = kChainItems / V;
+    static constexpr int VA = vwidth<IDT>();
+    static constexpr int SLOTS_A = kChainItems / VA;
     using L = local_t<IDT>;
     using C = carry_t<IDT, C64>;
     using X = vec<IDT, V>;
+    using XA = vec<IDT, VA>;
 };
 
 }  // namespace
@@ -218,6 +224,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_chain(LaunchArgs a) {
     using L = typename K::L;
     using C = typename K::C;
     using X = typename K::X;
+    using XA = typename K::XA;
+    constexpr int VA = K::VA, SLOTS_A = K::SLOTS_A;
     __shared__ L s_wt[P * kChainWaves];
     __shared__ C s_tot[2][P];
     __shared__ C s_w[kChainWaves];
@@ -265,14 +273,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_chain(LaunchArgs a) {
             // ---- phase A of chunk nxt into buffer buf ^ 1 ----
             const int b = buf ^ 1;
             const int64_t r0 = nxt * P;
-            X x[P][SLOTS];
+            XA x[P][SLOTS_A];
             SegInfo sc;
             if (chain_segment(a, tm, T, r0, P, REV, sc) &&
-                chain_load_full<IDT, V, SLOTS, REV>(a, sc, T, r0, x, w, l)) {
+                chain_load_full<IDT, VA, SLOTS_A, REV>(a, sc, T, r0, x, w, l)) {
                 // the common case: every tile full, all loads already issued
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    const L wt = chain_tile_sum<IDT, V, SLOTS>(x[p]);
+                    const L wt = chain_tile_sum<IDT, VA, SLOTS_A>(x[p]);
                     if (l == 0) s_wt[p * kChainWaves + w] = wt;
                 }
                 __syncthreads();
@@ -291,9 +299,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_chain(LaunchArgs a) {
                     const bool ok = r < T && chain_find(a, tm, REV ? T - 1 - r : r, si);   // uniform
                     if (ok) {
                         const int64_t u0 = ((REV ? T - 1 - r : r) - si.first) * a.tile;
-                        X xc[SLOTS];
-                        load_slots<IDT, SLOTS, V, false>(xc, si.in0, si, u0, w, l, REV);
-                        const L wt = chain_tile_sum<IDT, V, SLOTS>(xc);   // elements outside read as 0
+                        XA xc[SLOTS_A];
+                        load_slots<IDT, SLOTS_A, VA, false>(xc, si.in0, si, u0, w, l, REV);
+                        const L wt = chain_tile_sum<IDT, VA, SLOTS_A>(xc);   // elements outside read as 0
                         if (l == 0) s_wt[w] = wt;
                     }
                     __syncthreads();
