@@ -232,7 +232,8 @@ enum { DR_TUNE_TILE_PER_BLOCK = 1 };
 enum { DR_TUNE_SPECIALIZED = 2 };
 
 /* dr_tuning.flags for inclusive_scan, scan (sum) and scan_reduce: the
- * reduce-then-scan form (the default for all but small int32 scans): a
+ * reduce-then-scan form (the default except where dr_inclusive_scan names
+ * another): a
  * read-only pass forms every tile's total, one workgroup scans the
  * per-chunk totals, and the apply pass reads the input again, scans each
  * tile and adds its carry (three launches; the input is read twice). Max /
@@ -330,19 +331,21 @@ dr_status dr_transform_reduce(const dr_table* table, const dr_view* view, int32_
  * view over positions 0..i (CONCAT: across segments; BATCH: within the
  * element's segment), or over positions i.. (DR_SCAN_REVERSE).
  * The offset of a segment is the total of the segments before it (0 for the
- * first). By default the call runs three kernels: tile totals (reads the
- * input), a scan of per-chunk totals, and the tile scans plus carries
+ * first). The reduce-then-scan form runs three kernels: tile totals (reads
+ * the input), a scan of per-chunk totals, and the tile scans plus carries
  * (reads the input again, writes the output once); carries are sums in a
  * fixed order, so results repeat from run to run (DR_TUNE_TWO_PASS names
- * this form explicitly). DR_TUNE_TILE_PER_BLOCK selects one kernel whose
+ * this form explicitly; which form runs without a tuning is stated below). DR_TUNE_TILE_PER_BLOCK selects one kernel whose
  * tiles take their carries from a decoupled look-back, DR_TUNE_SPECIALIZED
  * the single pass with specialised waves, and DR_TUNE_CHAINED the chained
  * single pass (one range; the input read from HBM once); at most one form
- * flag. Without a tuning, int32 scans of at most 2^22 elements take the
- * look-back form (lower latency, exact either way), and larger int32 ->
+ * flag. Without a tuning: sums of the identity view over one range (CONCAT)
+ * of more than 2^22 F32 -> F32 or I32 -> I64 / I32 elements run the chained
+ * single pass; other int32 scans of at most 2^22 elements take the
+ * look-back form (lower latency, exact either way); other larger int32 ->
  * int64 scans of the identity view over tables of at most DR_SMALL_TABLE
  * rows use tiles of 64 items per thread (the output is twice the input's
- * size). Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
+ * size); everything else runs the reduce-then-scan form. Supported (in_dtype -> out_dtype): I32 -> I64 (exact), I32 -> I32
  * (exact modulo 2^32), F32 -> F32 and BF16 -> F32 (binary32 inside a tile,
  * binary64 carries unless DR_SCAN_CARRY_F32), F64 -> F64.
  * In-place (out[0] == in[0], same dtype size) is allowed; other overlap
