@@ -864,8 +864,8 @@ def main() -> int:
                          "of the step line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md describes how the "
-              "path would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (each GPU would scan its own "
+              "segments and exchange only segment totals); run with --gpus 1", file=sys.stderr)
         return 2
 
     if args.configs:
