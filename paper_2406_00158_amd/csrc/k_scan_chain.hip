@@ -4,12 +4,14 @@
 // offsets, here chained across the whole range).
 //
 // The two-pass form reads the input twice because a tile's carry is not
-// known when the tile is read. Here a workgroup keeps the second read in
-// its own XCD's L2: it takes chunks of P consecutive tiles (processing
-// order) from a counter and runs each chunk in two phases, one chunk
-// apart:
-//   phase A  reads the chunk with plain loads (the lines stay in L2), forms
-//            each tile's total (chain_tile_sum) and publishes the chunk's
+// known when the tile is read: its second pass starts when the first has
+// ended. Here a workgroup reads each chunk the second time one chunk after
+// the first, when the carries before it are known: it takes chunks of P
+// consecutive tiles (processing order) from a counter and runs each chunk
+// in two phases, one chunk apart:
+//   phase A  reads the chunk with plain loads (so that the lines may stay in
+//            the caches for the re-read), forms each tile's total
+//            (chain_tile_sum) and publishes the chunk's
 //            total; the last chunk of a superblock of kChainSB chunks to
 //            arrive (an arrival counter) sums the superblock's totals and
 //            publishes the running carry at its end,
@@ -17,8 +19,12 @@
 //   phase B  runs after the workgroup's next chunk has been through phase
 //            A: the chunk's carry is E(sb - 1) plus the sum of the totals
 //            of the chunks before it in its superblock; the chunk is read
-//            again (from L2, non-temporal: the last use), each tile
-//            scanned in registers, its carry added, and written once.
+//            again (non-temporal: the last use), each tile scanned in
+//            registers, its carry added, and written once.
+// (At 2 workgroups per CU the re-read mostly misses the XCD's 4 MiB L2:
+// the counters see the input fetched twice. Holding the chunk in LDS
+// between the phases instead, which removes that traffic, measured no
+// faster: the pass is bound by what each workgroup keeps in flight.)
 // Every sum of published totals runs over a fixed shape (one total per
 // thread, absent ones 0, a DPP wave sum, the waves in order), so results
 // repeat exactly and do not depend on timing or on the grid. A workgroup
@@ -113,8 +119,8 @@ __device__ __forceinline__ bool chain_segment(const LaunchArgs& a, const TileMap
 
 // The loads of a chunk whose P tiles lie in the segment `si` and are all
 // full (whole inside it, rows aligned): unchecked, back to back; plain loads
-// in phase A (the lines stay in L2), non-temporal ones (NT) for phase B's
-// re-read. Returns false, loading nothing, when a tile is not full (the
+// in phase A (the lines may stay cached for the re-read), non-temporal ones
+// (NT) for phase B's re-read. Returns false, loading nothing, when a tile is not full (the
 // caller then takes the tiles one by one, checked).
 template <int IDT, int V, int SLOTS, bool REV, bool NT = false, int P>
 __device__ __forceinline__ bool chain_load_full(const LaunchArgs& a, const SegInfo& si, int64_t T, int64_t r0,
@@ -377,8 +383,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_chain(LaunchArgs a) {
                 const int64_t t = REV ? T - 1 - r : r;
                 const int64_t u0 = (t - si.first) * a.tile;
                 const bool full = tile_full<V, SLOTS>(si, u0);
-                // the second and last read (from L2): non-temporal, so the
-                // lines leave room for the chunks still to be re-read
+                // the second and last read: non-temporal, so the lines
+                // leave room for the chunks still to be re-read
                 X xb[SLOTS];
                 load_slots<IDT, SLOTS, V, true>(xb, si.in0, si, u0, w, l, REV);
                 L v[SLOTS][V];
@@ -412,8 +418,8 @@ hipError_t launch_scan_chain(const LaunchArgs& a, int64_t, hipStream_t stream) {
     if (!(a.flags & kFlagChained)) return hipErrorNotSupported;
     hipError_t e = launch_prologue(a, stream);
     if (e != hipSuccess) return e;
-    // two workgroups per CU: more leave too many chunks between a chunk's
-    // two reads for the L2 of an XCD (4 MiB) to keep it
+    // two workgroups per CU: the registers allow no more (187-238 VGPRs),
+    // and fewer measured slower
     static const int per_dev = [] {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
