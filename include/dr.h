@@ -17,10 +17,12 @@
  *    kernel that runs the algorithm (no intermediate array).
  *  - The algorithms are for_each, reduce and inclusive_scan over the
  *    segments (section 4.3; Algorithms 3 and 4). Here each call covers all
- *    segments at once (the paper launches per segment). The scan takes its
- *    cross-segment offsets from a read-only first pass of tile totals and
- *    writes every output once (the paper's second pass re-reads and
- *    re-writes the output).
+ *    segments at once (the paper launches per segment). The scan writes
+ *    every output once: its cross-segment offsets come from a read-only
+ *    first pass of tile totals (the two-pass form) or from chunk totals
+ *    published one chunk ahead (the chained single pass, the default for
+ *    long ranges); the paper's second pass re-reads and re-writes the
+ *    output.
  *
  * Conventions shared by every entry point:
  *  - Ownership: the caller owns every buffer (inputs, outputs, the device
@@ -242,9 +244,9 @@ enum { DR_TUNE_TWO_PASS = 4 };
 
 /* dr_tuning.flags for inclusive_scan and scan (sums): the chained single
  * pass. Workgroups claim chunks of 4 tiles from a counter; each chunk is
- * read once from HBM to publish its total (its lines stay in the L2 cache)
- * and read again from L2 one chunk later, when its carry is known, to be
- * scanned and written. Carries are sums over a fixed shape (chunk totals
+ * read once to publish its total and read again one chunk later, when its
+ * carry is known, to be scanned and written (the re-read mostly misses the
+ * L2 cache: the memory counters see the input fetched twice). Carries are sums over a fixed shape (chunk totals
  * folded per superblock of 128 chunks, running carries chained across
  * superblocks), so results repeat from run to run. Built for one range
  * (CONCAT) of sums of the identity view: F32 -> F32 (binary64 carries, or
